@@ -1,0 +1,281 @@
+"""Pins of the oracle's MHD right-hand side and full RK3 step (CPU only).
+
+* Against an independent symbolic evaluation of Eqs. B.1-B.4 (sympy, with
+  continuous operators: j = curl(curl A)/mu0 and the conduction term as
+  div(K grad T)/(rho T) with T from the equation of state), the oracle's
+  RHS converges at sixth order under grid refinement.  A dropped term, a
+  wrong sign or a swapped index stops the convergence.
+* A uniform state has zero RHS; a cyclic relabelling of the axes permutes
+  the RHS (isotropy); periodic sums of the divergence and of the resistive
+  term vanish.
+* Linear waves: an entropy/contact wave is advected exactly as the RK3
+  polynomial of the discrete advection symbol; small-amplitude sound and
+  Alfven waves follow the cubic Taylor propagator of their discrete
+  linearised systems.
+"""
+import math
+
+import numpy as np
+import pytest
+import sympy as sp
+
+from paper_2103_01597_amd import inputs
+
+TWO_PI = 2 * math.pi
+
+# Non-trivial constants so that misplaced cp, mu0, rho0, zeta, B_ext show up.
+PHYS = dict(cs0=1.1, gamma=5.0 / 3.0, cp=1.5, lnrho0=0.1, mu0=1.3, nu=0.05,
+            zeta=0.02, eta=0.04, K=0.03, bext=(0.1, -0.2, 0.05))
+
+X, Y, Z = sp.symbols("x y z", real=True)
+XYZ = (X, Y, Z)
+
+
+def _analytic_fields():
+    s = sp.sin
+    c = sp.cos
+    return [
+        0.2 * s(X + 2 * Y - Z + 0.3) + 0.1 * c(2 * Z),               # lnrho
+        0.3 * s(X + Y + 0.1) + 0.2 * c(2 * Z - X),                   # ux
+        0.25 * c(Y - Z + 0.5) + 0.15 * s(X + 2 * Y),                 # uy
+        0.2 * s(X - Y + Z) + 0.1 * c(X + 0.7),                       # uz
+        0.15 * c(X - 2 * Y + 0.2) + 0.1 * s(Y + Z),                  # ss
+        0.3 * s(2 * Y + Z + 0.4) + 0.2 * c(X - Y),                   # Ax
+        0.25 * c(X + Z - 0.3) + 0.1 * s(2 * X - Y + Z),              # Ay
+        0.2 * s(X + Y - 2 * Z) + 0.15 * c(Y - 0.6),                  # Az
+    ]
+
+
+def _symbolic_rhs(fields, P):
+    """Eqs. B.1-B.4 with continuous operators (H = C = 0, K constant)."""
+    grad = lambda f: sp.Matrix([sp.diff(f, v) for v in XYZ])
+    div = lambda F: sum(sp.diff(F[i], XYZ[i]) for i in range(3))
+    curl = lambda F: sp.Matrix([sp.diff(F[2], Y) - sp.diff(F[1], Z),
+                                sp.diff(F[0], Z) - sp.diff(F[2], X),
+                                sp.diff(F[1], X) - sp.diff(F[0], Y)])
+    lap = lambda f: sum(sp.diff(f, v, 2) for v in XYZ)
+    lnrho, ux, uy, uz, ss, ax, ay, az = fields
+    u = sp.Matrix([ux, uy, uz])
+    A = sp.Matrix([ax, ay, az])
+    g, cp = P["gamma"], P["cp"]
+    rho = sp.exp(lnrho)
+    cs2 = P["cs0"] ** 2 * sp.exp(g * ss / cp + (g - 1) * (lnrho - P["lnrho0"]))
+    T = cs2 / (cp * (g - 1))
+    B = curl(A) + sp.Matrix(P["bext"])
+    j = curl(B) / P["mu0"]
+    G = sp.Matrix(3, 3, lambda i, k: sp.diff(u[i], XYZ[k]))
+    divu = div(u)
+    S = (G + G.T) / 2 - sp.eye(3) * divu / 3
+    gl = grad(lnrho)
+    d_lnrho = -(u.dot(gl)) - divu
+    lapu = sp.Matrix([lap(u[i]) for i in range(3)])
+    d_u = (-(G * u) - cs2 * (grad(ss) / cp + gl) + j.cross(B) / rho
+           + P["nu"] * (lapu + grad(divu) / 3 + 2 * S * gl) + P["zeta"] * grad(divu))
+    SS = sum(S[i, k] ** 2 for i in range(3) for k in range(3))
+    d_ss = -(u.dot(grad(ss))) + (P["K"] * lap(T) + P["eta"] * P["mu0"] * j.dot(j)
+                                 + 2 * rho * P["nu"] * SS + P["zeta"] * rho * divu ** 2) / (rho * T)
+    d_A = u.cross(B) + P["eta"] * sp.Matrix([lap(A[i]) for i in range(3)])
+    return [d_lnrho, d_u[0], d_u[1], d_u[2], d_ss, d_A[0], d_A[1], d_A[2]]
+
+
+@pytest.fixture(scope="module")
+def analytic():
+    f = _analytic_fields()
+    r = _symbolic_rhs(f, PHYS)
+    mods = ["numpy"]
+    return ([sp.lambdify(XYZ, e, mods) for e in f], [sp.lambdify(XYZ, e, mods) for e in r])
+
+
+def _eval_on_grid(fns, n, lengths=(TWO_PI,) * 3):
+    nx, ny, nz = n
+    x = np.arange(nx) * lengths[0] / nx
+    y = np.arange(ny) * lengths[1] / ny
+    z = np.arange(nz) * lengths[2] / nz
+    Zg, Yg, Xg = np.meshgrid(z, y, x, indexing="ij")
+    return np.stack([np.broadcast_to(fn(Xg, Yg, Zg), Xg.shape) for fn in fns]).astype(np.float64)
+
+
+def _params(oracle_mod, n, lengths=(TWO_PI,) * 3, **over):
+    kw = dict(PHYS)
+    kw.update(over)
+    return oracle_mod.Params(nx=n[0], ny=n[1], nz=n[2], lx=lengths[0], ly=lengths[1],
+                             lz=lengths[2], **kw)
+
+
+def test_rhs_sixth_order_convergence(oracle_mod, analytic):
+    ffn, rfn = analytic
+    errs = []
+    for n in (16, 32, 64):
+        f = _eval_on_grid(ffn, (n, n, n))
+        exact = _eval_on_grid(rfn, (n, n, n))
+        got = oracle_mod.rhs(f, _params(oracle_mod, (n, n, n)))
+        errs.append([np.max(np.abs(got[q] - exact[q])) / np.max(np.abs(exact[q])) for q in range(8)])
+    errs = np.array(errs)
+    r1 = errs[0] / errs[1]
+    r2 = errs[1] / errs[2]
+    assert np.all(errs[2] < 1e-5), errs
+    assert np.all(r1 > 35) and np.all((r2 > 50) & (r2 < 80)), (r1, r2)
+
+
+def test_rhs_convergence_anisotropic_box(oracle_mod):
+    """Unequal box lengths and cell counts per axis (fields periodic on it)."""
+    L = (TWO_PI, 2 * TWO_PI, TWO_PI)
+    f_sym = [e.subs(Y, Y / 2) for e in _analytic_fields()]  # period 4*pi in y
+    r_sym = _symbolic_rhs(f_sym, PHYS)
+    ffn = [sp.lambdify(XYZ, e, "numpy") for e in f_sym]
+    rfn = [sp.lambdify(XYZ, e, "numpy") for e in r_sym]
+    errs = []
+    for n in ((16, 24, 20), (32, 48, 40)):
+        f = _eval_on_grid(ffn, n, L)
+        exact = _eval_on_grid(rfn, n, L)
+        got = oracle_mod.rhs(f, _params(oracle_mod, n, L))
+        errs.append([np.max(np.abs(got[q] - exact[q])) / np.max(np.abs(exact[q])) for q in range(8)])
+    errs = np.array(errs)
+    assert np.all(errs[0] / errs[1] > 40), errs
+
+
+def test_uniform_state_has_zero_rhs(oracle_mod):
+    n = (8, 7, 6)
+    f = np.empty((8, n[2], n[1], n[0]))
+    for q, v in enumerate([0.3, -0.2, 0.5, 0.1, 0.7, 0.0, 0.0, 0.0]):
+        f[q] = v
+    got = oracle_mod.rhs(f, _params(oracle_mod, n, bext=(0.0, 0.0, 0.0)))
+    assert np.max(np.abs(got)) < 1e-13
+    # with a uniform B_ext only the induction term u x B survives
+    b = PHYS["bext"]
+    got = oracle_mod.rhs(f, _params(oracle_mod, n))
+    u = (-0.2, 0.5, 0.1)
+    uxb = (u[1] * b[2] - u[2] * b[1], u[2] * b[0] - u[0] * b[2], u[0] * b[1] - u[1] * b[0])
+    assert np.max(np.abs(got[:5])) < 1e-13
+    for a in range(3):
+        assert np.max(np.abs(got[5 + a] - uxb[a])) < 1e-15
+
+
+def test_axis_cycle_equivariance(oracle_mod):
+    n = 12
+    f = inputs.fourier_modes((n, n, n), 3, 0.2, seed=21)
+    P = _params(oracle_mod, (n, n, n))
+    r = oracle_mod.rhs(f, P)
+    # new axes (x', y', z') = (y, z, x): scalars s'[a,b,c] = s[b,c,a]
+    perm = lambda a: np.ascontiguousarray(np.transpose(a, (2, 0, 1)))
+    vec = lambda v: [perm(v[1]), perm(v[2]), perm(v[0])]
+
+    def cyc(g):
+        return np.stack([perm(g[0]), *vec(g[1:4]), perm(g[4]), *vec(g[5:8])])
+
+    b = PHYS["bext"]
+    P2 = _params(oracle_mod, (n, n, n), bext=(b[1], b[2], b[0]))
+    r2 = oracle_mod.rhs(cyc(f), P2)
+    assert np.max(np.abs(r2 - cyc(r))) < 1e-12 * np.max(np.abs(r))
+
+
+def test_periodic_sums(oracle_mod):
+    n = (10, 9, 8)
+    f = inputs.fourier_modes(n, 3, 0.1, seed=22)
+    P = _params(oracle_mod, n)
+    r = oracle_mod.rhs(f, P)
+    # B.1: sum(d lnrho/dt + u.grad lnrho) = -sum(div u) = 0
+    adv = sum(f[1 + a] * oracle_mod.deriv(f[0], op) for a, op in enumerate(("d1x", "d1y", "d1z")))
+    tot = r[0] + adv
+    assert abs(tot.sum()) < 1e-12 * np.abs(tot).sum()
+    # B.4 with u = 0: sum(eta lap A) = 0
+    g = f.copy()
+    g[1:4] = 0.0
+    rA = oracle_mod.rhs(g, _params(oracle_mod, n, bext=(0.0, 0.0, 0.0)))[5:8]
+    for q in range(3):
+        assert abs(rA[q].sum()) < 1e-12 * np.abs(rA[q]).sum()
+
+
+def test_mass_rate_converges_to_zero(oracle_mod):
+    """The ln(rho) form is not conservative, so the discrete mass rate
+    sum(exp(lnrho) d lnrho/dt) is nonzero, but it vanishes at least at the
+    scheme's order (2^6 per grid doubling) as the grid resolves the state."""
+    rates = []
+    for n in (24, 48):
+        f = inputs.fourier_modes((n, n, n), 4, 0.3, seed=5)
+        r = oracle_mod.rhs(f, _params(oracle_mod, (n, n, n)))
+        rho = np.exp(f[0])
+        rates.append(abs(np.sum(rho * r[0])) / np.sum(np.abs(rho * r[0])))
+    assert rates[0] < 1e-7 and rates[1] < rates[0] / 60, rates
+
+
+def _rk3_poly(z):
+    return 1 + z + z * z / 2 + z ** 3 / 6
+
+
+def _ktilde(k, h):
+    t = k * h
+    return (45 * math.sin(t) - 9 * math.sin(2 * t) + math.sin(3 * t)) / (30 * h)
+
+
+def _khat2(k, h):
+    t = k * h
+    return (490 - 540 * math.cos(t) + 54 * math.cos(2 * t) - 4 * math.cos(3 * t)) / (180 * h * h)
+
+
+def test_contact_wave_exact(oracle_mod):
+    """u = U x, lnrho = eps cos(kx), s = -lnrho (cp = 1), no diffusion: the
+    pressure gradient is identically zero and lnrho, s are advected by
+    -U D_x, so each step multiplies the mode by R(-i U k~ dt)."""
+    n, k, U, eps, dt, N = 24, 3, 0.7, 0.5, 0.02, 15
+    x = np.arange(n) * TWO_PI / n
+    f = np.zeros((8, 4, 4, n))
+    f[0] = eps * np.cos(k * x)
+    f[4] = -f[0]
+    f[1] = U
+    P = _params(oracle_mod, (n, 4, 4), cp=1.0, nu=0.0, eta=0.0, K=0.0, zeta=0.0,
+                bext=(0.0, 0.0, 0.0))
+    out = oracle_mod.step(f, dt, P, N)
+    amp = _rk3_poly(-1j * U * _ktilde(k, TWO_PI / n) * dt) ** N
+    expect = eps * np.real(amp * np.exp(1j * k * x))
+    assert np.max(np.abs(out[0] - expect)) < 1e-13
+    assert np.max(np.abs(out[4] + expect)) < 1e-13
+    assert np.max(np.abs(out[1] - U)) < 1e-13
+    assert np.max(np.abs(out[2:4])) < 1e-13 and np.max(np.abs(out[5:])) < 1e-13
+
+
+def test_linear_sound_wave(oracle_mod):
+    n, k, eps, dt, N = 16, 2, 1e-6, 0.01, 20
+    nu, K, g, cs0 = 0.05, 0.03, 5.0 / 3.0, 1.0
+    h = TWO_PI / n
+    kt, kh2 = _ktilde(k, h), _khat2(k, h)
+    M = np.array([[0, -1j * kt, 0],
+                  [-1j * cs0 ** 2 * kt, -(4.0 / 3.0) * nu * kh2, -1j * cs0 ** 2 * kt],
+                  [-K * (g - 1) * kh2, 0, -K * g * kh2]])
+    D = dt * M
+    Pstep = np.eye(3) + D + D @ D / 2 + D @ D @ D / 6
+    v = np.linalg.matrix_power(Pstep, N) @ np.array([1.0, 0.3j, -0.5])
+    x = np.arange(n) * h
+    f = np.zeros((8, 4, 4, n))
+    mode = np.exp(1j * k * x)
+    f[0] = eps * np.real(1.0 * mode)
+    f[1] = eps * np.real(0.3j * mode)
+    f[4] = eps * np.real(-0.5 * mode)
+    P = _params(oracle_mod, (n, 4, 4), cs0=cs0, gamma=g, cp=1.0, lnrho0=0.0, nu=nu,
+                zeta=0.0, eta=0.0, K=K, bext=(0.0, 0.0, 0.0))
+    out = oracle_mod.step(f, dt, P, N)
+    for q, vi in zip((0, 1, 4), v):
+        expect = eps * np.real(vi * mode)
+        assert np.max(np.abs(out[q] - expect)) < 1e-4 * eps, q
+
+
+def test_linear_alfven_wave(oracle_mod):
+    n, k, eps, dt, N = 16, 2, 1e-6, 0.01, 20
+    nu, eta, B0, mu0 = 0.05, 0.04, 0.8, 1.3
+    h = TWO_PI / n
+    kh2 = _khat2(k, h)
+    M = np.array([[-nu * kh2, B0 * kh2 / mu0], [-B0, -eta * kh2]])
+    D = dt * M
+    Pstep = np.eye(2) + D + D @ D / 2 + D @ D @ D / 6
+    v = np.linalg.matrix_power(Pstep, N) @ np.array([1.0, 0.4j])
+    x = np.arange(n) * h
+    mode = np.exp(1j * k * x)
+    f = np.zeros((8, 4, 4, n))
+    f[2] = eps * np.real(1.0 * mode)
+    f[7] = eps * np.real(0.4j * mode)
+    P = _params(oracle_mod, (n, 4, 4), cs0=1.0, cp=1.0, lnrho0=0.0, nu=nu, zeta=0.0,
+                eta=eta, K=0.0, mu0=mu0, bext=(B0, 0.0, 0.0))
+    out = oracle_mod.step(f, dt, P, N)
+    for q, vi in zip((2, 7), v):
+        expect = eps * np.real(vi * mode)
+        assert np.max(np.abs(out[q] - expect)) < 1e-4 * eps, q

@@ -1,0 +1,169 @@
+#!/usr/bin/env python3
+"""Throughput of the fused sixth-order MHD RK3 path on one MI355X.
+
+Metric: GCUPS per RK3 substep = 3 * (interior cells) * steps / time / 1e9,
+for FP64 (the headline `value`) and for FP32 storage with the compensated
+update (reported beside it), on the 512^3 precision-comparison workload:
+8 fields initialised as 1e-2 * (sum of 4 seeded Fourier modes, |k| <= 8),
+cs0 = 1, gamma = 5/3, nu = eta = chi = 5e-3, dt = 1e-3, periodic halo
+filled before every substep.  Inputs are resident in HBM before timing.
+
+One timed step = 3 x (halo fill + fused RHS/RK3 substep), exactly the
+launch sequence of mhd_step.  HIP events on the launch stream bracket the
+whole timed region and every fused-substep launch; the per-launch average
+gives the roofline entry of the dominant kernel.
+
+`--gpus N` with N > 1 exits: the path is one GPU's share of the domain and
+has no multi-GPU mode.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+# Compulsory HBM bytes per interior cell of the fused substep (8 fields):
+# read f_in, write w and f_out, plus read w for s > 0; F32C also reads and
+# writes the compensation array.
+BYTES_PER_CELL = {
+    "f64": (3 * 8 * 8, 4 * 8 * 8, 4 * 8 * 8),   # 192, 256, 256
+    "f32c": (5 * 8 * 4, 6 * 8 * 4, 6 * 8 * 4),  # 160, 192, 192
+    "f32": (3 * 8 * 4, 4 * 8 * 4, 4 * 8 * 4),   # 96, 128, 128
+}
+
+
+def run_precision(mhd, inputs, torch, wl, prec, steps, warmup):
+    n = wl["shape"]
+    cells = n[0] * n[1] * n[2]
+    S = mhd.Solver(*n, prec, lengths=wl.get("lengths", (2 * math.pi,) * 3))
+    host =inputs.fourier_modes(n, wl["kmax"], wl["amp"], wl["seed"])
+    bufs = [S.upload(host), S.empty()]
+    del host
+    w = S.zeros()
+    comp = S.zeros() if prec == "f32c" else None
+    dt = wl["dt"]
+    stream = torch.cuda.current_stream()
+    cur = S.step(bufs, 0, w, comp, dt, warmup)
+    torch.cuda.synchronize()
+
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(3)] for _ in range(steps)]
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t0.record(stream)
+    for k in range(steps):
+        for s in range(3):
+            S.halo_periodic(bufs[cur])
+            ev[k][s][0].record(stream)
+            S.rk3_substep(s, bufs[cur], bufs[1 - cur], w, comp, dt)
+            ev[k][s][1].record(stream)
+            cur ^= 1
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = t0.elapsed_time(t1)
+    kern_ms = [[ev[k][s][0].elapsed_time(ev[k][s][1]) for s in range(3)] for k in range(steps)]
+    sum_kern_ms = sum(sum(r) for r in kern_ms)
+    alg_bytes = steps * cells * sum(BYTES_PER_CELL[prec])
+    achieved = alg_bytes / (sum_kern_ms * 1e-3) / 1e9
+    nonfinite = S.reduce(bufs[cur], 0, "nonfinite")
+    res = dict(
+        gcups=3 * cells * steps / (total_ms * 1e-3) / 1e9,
+        ms_per_step=total_ms / steps,
+        wall_s=wall,
+        kernel_ms_avg=sum_kern_ms / (3 * steps),
+        kernel_ms_by_substep=[sum(r[s] for r in kern_ms) / steps for s in range(3)],
+        kernel_gbs=achieved,
+        kernel_gcups=3 * cells * steps / (sum_kern_ms * 1e-3) / 1e9,
+        nonfinite=nonfinite,
+    )
+    S.close()
+    del bufs, w, comp
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(inputs, wl):
+    """The oracle as it stands, one RK3 step on a 128^3 grid of the same
+    workload recipe (a bounded sample: about 10-30 s of host work)."""
+    import oracle
+    n = (128, 128, 128)
+    f = inputs.fourier_modes(n, wl["kmax"], wl["amp"], wl["seed"])
+    p = oracle.Params(*n)
+    t = time.perf_counter()
+    oracle.step(f, wl["dt"], p, 1)
+    dt = time.perf_counter() - t
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=3 * n[0] * n[1] * n[2] / dt / 1e9, unit="GCUPS", cores=threads,
+                kind="oracle",
+                sample=f"one RK3 step (3 substeps) of the FP64 oracle on 128^3 with the "
+                       f"same 8-field Fourier-mode recipe, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precisions", default="f64,f32c")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this path is one GPU's share of the domain and has no multi-GPU "
+              "mode; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2103_01597_amd import inputs, mhd
+    mhd.lib()
+    torch.cuda.set_device(0)
+    wl = inputs.WORKLOADS["prec512"]
+    results = {}
+    for prec in args.precisions.split(","):
+        results[prec] = run_precision(mhd, inputs, torch, wl, prec, args.steps, args.warmup)
+        print(f"# {prec}: {json.dumps(results[prec])}", file=sys.stderr, flush=True)
+
+    main_prec = "f64" if "f64" in results else next(iter(results))
+    r = results[main_prec]
+    line = {
+        "metric": "GCUPS per RK3 substep at 512^3 (FP64; FP32-storage compensated beside it)",
+        "value": round(r["gcups"], 4),
+        "unit": "GCUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": main_prec,
+        "data": "synthetic",
+        "config": {"workload": "prec512: 512^3 periodic, 8 fields, 1e-2 x 4 Fourier modes "
+                               "|k|<=8 seed 3, dt 1e-3, halo fill every substep",
+                   "grid": [512, 512, 512], "precision": main_prec},
+        "roofline": {"bound": "hbm", "achieved": round(r["kernel_gbs"], 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(r["kernel_gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "fused RHS+RK3 substep",
+                     "kernel_ms_avg": round(r["kernel_ms_avg"], 4)},
+    }
+    for prec, rr in results.items():
+        if prec != main_prec:
+            line[f"{prec}_gcups"] = round(rr["gcups"], 4)
+            line[f"{prec}_roofline_frac"] = round(rr["kernel_gbs"] / HBM_PEAK_GBS, 4)
+            line[f"{prec}_kernel_ms_avg"] = round(rr["kernel_ms_avg"], 4)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(inputs, wl)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

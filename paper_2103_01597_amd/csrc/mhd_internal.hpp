@@ -1,0 +1,152 @@
+// Internal declarations of the MHD library: launch parameters, the
+// right-hand-side assembly shared by every fused kernel, and the kernel
+// launchers.  gfx950 (CDNA4) only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mhd.h"
+
+namespace mhd {
+
+constexpr int R = 3;   // stencil radius (sixth order, Section 4)
+constexpr int NQ = 8;  // fields of Table B.1
+
+// Grid geometry as the kernels see it.
+struct Grid {
+    int nx, ny, nz;
+    int mx, my, mz;
+    int64_t fstride;  // elements between fields
+    int mxy;          // mx*my (one padded plane; < 2^31 for every supported size)
+    int interior;     // (3*my + 3)*mx + 3
+};
+
+// Physics constants and grid spacings, in double; kernels convert.
+struct Phys {
+    double inv_h[3];       // 1/h_i
+    double cs0sq, gamma, inv_cp, lnrho0, mu0, inv_mu0, nu, zeta, eta, K;
+    double bext[3];
+    double gamma_m1;       // gamma - 1
+    double cp_gm1;         // cp*(gamma - 1)
+};
+
+// Williamson 2N RK3 (the scheme cited in Section 4).
+constexpr double RK_ALPHA[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
+constexpr double RK_BETA[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+
+// Sixth-order central weights, expressed as multipliers of differences:
+// D1 f = [45 d1 - 9 d2 + d3] / (60 h),    d_m = f(+m) - f(-m)
+// D2 f = [-490 f0 + 270 s1 - 27 s2 + 2 s3] / (180 h^2),  s_m = f(+m) + f(-m)
+// Dab f = [270 e1 - 27 e2 + 2 e3] / (720 h_a h_b), e_m = P_m - Q_m with
+//   P_m = f(+m,+m) + f(-m,-m), Q_m = f(+m,-m) + f(-m,+m) on the (a,b) plane.
+constexpr double C1_1 = 45.0 / 60.0, C1_2 = -9.0 / 60.0, C1_3 = 1.0 / 60.0;
+constexpr double C2_0 = -490.0 / 180.0, C2_1 = 270.0 / 180.0, C2_2 = -27.0 / 180.0,
+                 C2_3 = 2.0 / 180.0;
+constexpr double CM_1 = 270.0 / 720.0, CM_2 = -27.0 / 720.0, CM_3 = 2.0 / 720.0;
+
+// Everything the right-hand side of Eqs. B.1-B.4 reads at one cell.
+// R: the arithmetic type of the physics (double, or float for FP32 storage).
+template <typename Rt>
+struct Derivs {
+    Rt lnrho, ux, uy, uz, ss;          // centre values (A enters only via derivatives)
+    Rt gl[3], gs[3];                   // grad lnrho, grad s
+    Rt gu[3][3];                       // gu[a][b] = d u_a / d x_b
+    Rt dAz_dy, dAy_dz, dAx_dz, dAz_dx, dAy_dx, dAx_dy;
+    Rt lapl, laps;                     // Laplacians of lnrho and s
+    Rt lapu[3], gdu[3];                // lap u and grad(div u)
+    Rt lapA[3], jmu[3];                // lap A and mu0*j = grad(div A) - lap A
+};
+
+// Right-hand side of Eqs. B.1-B.4 (H = C = 0, K constant) with the ideal
+// gas closure cs^2 = cs0^2 exp(gamma s/cp + (gamma-1)(lnrho - lnrho0)),
+// cp (gamma-1) T = cs^2; B = curl A + B_ext; S the traceless rate of shear.
+template <typename Rt>
+__device__ __forceinline__ void rhs_physics(const Derivs<Rt>& d, const Phys& P, Rt out[NQ])
+{
+    const Rt gamma = Rt(P.gamma), inv_cp = Rt(P.inv_cp), gm1 = Rt(P.gamma_m1);
+    const Rt nu = Rt(P.nu), zeta = Rt(P.zeta), eta = Rt(P.eta);
+    const Rt u[3] = {d.ux, d.uy, d.uz};
+
+    const Rt inv_rho = exp(-d.lnrho);
+    const Rt cs2 = Rt(P.cs0sq) * exp(gamma * d.ss * inv_cp + gm1 * (d.lnrho - Rt(P.lnrho0)));
+    const Rt inv_T = Rt(P.cp_gm1) / cs2;
+
+    const Rt divu = d.gu[0][0] + d.gu[1][1] + d.gu[2][2];
+    Rt S[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            S[a][b] = Rt(0.5) * (d.gu[a][b] + d.gu[b][a]);
+    const Rt third_divu = divu * Rt(1.0 / 3.0);
+    S[0][0] -= third_divu;
+    S[1][1] -= third_divu;
+    S[2][2] -= third_divu;
+
+    const Rt B[3] = {d.dAz_dy - d.dAy_dz + Rt(P.bext[0]),
+                     d.dAx_dz - d.dAz_dx + Rt(P.bext[1]),
+                     d.dAy_dx - d.dAx_dy + Rt(P.bext[2])};
+    const Rt inv_mu0 = Rt(P.inv_mu0);
+    const Rt J[3] = {d.jmu[0] * inv_mu0, d.jmu[1] * inv_mu0, d.jmu[2] * inv_mu0};
+
+    // B.1
+    out[0] = -(u[0] * d.gl[0] + u[1] * d.gl[1] + u[2] * d.gl[2]) - divu;
+
+    // B.2
+    const Rt jxB[3] = {J[1] * B[2] - J[2] * B[1], J[2] * B[0] - J[0] * B[2],
+                       J[0] * B[1] - J[1] * B[0]};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const Rt adv = u[0] * d.gu[a][0] + u[1] * d.gu[a][1] + u[2] * d.gu[a][2];
+        const Rt Sgl = S[a][0] * d.gl[0] + S[a][1] * d.gl[1] + S[a][2] * d.gl[2];
+        const Rt pres = -cs2 * (d.gs[a] * inv_cp + d.gl[a]);
+        const Rt visc = nu * (d.lapu[a] + d.gdu[a] * Rt(1.0 / 3.0) + Rt(2) * Sgl);
+        out[1 + a] = -adv + pres + jxB[a] * inv_rho + visc + zeta * d.gdu[a];
+    }
+
+    // B.3 divided by rho*T
+    Rt glnT2 = Rt(0), SS = Rt(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const Rt g = gamma * d.gs[a] * inv_cp + gm1 * d.gl[a];
+        glnT2 += g * g;
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            SS += S[a][b] * S[a][b];
+    }
+    const Rt laplnT = gamma * d.laps * inv_cp + gm1 * d.lapl;
+    const Rt jj = J[0] * J[0] + J[1] * J[1] + J[2] * J[2];
+    const Rt udgs = u[0] * d.gs[0] + u[1] * d.gs[1] + u[2] * d.gs[2];
+    out[4] = -udgs + Rt(P.K) * inv_rho * (laplnT + glnT2) +
+             inv_T * (eta * Rt(P.mu0) * jj * inv_rho + Rt(2) * nu * SS + zeta * divu * divu);
+
+    // B.4
+    out[5] = u[1] * B[2] - u[2] * B[1] + eta * d.lapA[0];
+    out[6] = u[2] * B[0] - u[0] * B[2] + eta * d.lapA[1];
+    out[7] = u[0] * B[1] - u[1] * B[0] + eta * d.lapA[2];
+}
+
+// Kahan-compensated addition f <- f + y with running compensation c
+// (FP32 storage variant).  Written with explicit round-to-nearest
+// operations so the compiler cannot fuse or reassociate them.
+__device__ __forceinline__ float kahan_add(float f, float y, float& c)
+{
+    const float yc = __fsub_rn(y, c);
+    const float t = __fadd_rn(f, yc);
+    c = __fsub_rn(__fsub_rn(t, f), yc);
+    return t;
+}
+
+// ------------------------------------------------------------ launchers
+hipError_t launch_halo(const Grid& g, void* fields, int elem_size, hipStream_t st);
+
+hipError_t launch_rk3(const Grid& g, const Phys& P, int precision, int s, const void* f_in,
+                      void* f_out, void* w, void* comp, double dt, hipStream_t st);
+
+hipError_t launch_reduce(const Grid& g, const void* field, int elem_size, int op,
+                         double* partials, int npartials, double* result, hipStream_t st);
+
+constexpr int REDUCE_BLOCKS = 1024;
+
+}  // namespace mhd

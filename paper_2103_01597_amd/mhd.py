@@ -1,0 +1,190 @@
+"""Python binding of libmhd.so (include/mhd.h): argument marshalling only.
+
+Every step of the path runs in the library's HIP kernels.  PyTorch serves
+as the device allocator and supplies the stream (the current torch stream
+unless one is passed).  If the library is not built, :func:`lib` raises --
+there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmhd.so")
+
+F64, F32C, F32 = 0, 1, 2
+PRECISIONS = {"f64": F64, "f32c": F32C, "f32": F32}
+RED_OPS = {"sum": 0, "sumsq": 1, "maxabs": 2, "min": 3, "max": 4, "sumexp": 5, "nonfinite": 6}
+FIELD_NAMES = ("lnrho", "ux", "uy", "uz", "ss", "ax", "ay", "az")
+STATUS = {0: "MHD_OK", 1: "MHD_ERR_INVALID", 2: "MHD_ERR_NO_DEVICE", 3: "MHD_ERR_DEVICE",
+          4: "MHD_ERR_NOMEM"}
+
+# every symbol declared in include/mhd.h
+EXPORTS = ("mhd_config_default", "mhd_init", "mhd_finalize", "mhd_strerror",
+           "mhd_halo_periodic", "mhd_rk3_substep", "mhd_step", "mhd_reduce")
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("precision", ctypes.c_int32),
+                ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double),
+                ("cs0", ctypes.c_double), ("gamma", ctypes.c_double), ("cp", ctypes.c_double),
+                ("lnrho0", ctypes.c_double), ("mu0", ctypes.c_double), ("nu", ctypes.c_double),
+                ("zeta", ctypes.c_double), ("eta", ctypes.c_double), ("K", ctypes.c_double),
+                ("bext", ctypes.c_double * 3)]
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in
+                ("mx", "my", "mz", "field_stride", "elem_size", "interior_offset", "total_elems")]
+
+
+class MhdError(RuntimeError):
+    def __init__(self, fn, rc):
+        super().__init__(f"{fn} failed: {STATUS.get(rc, rc)}")
+        self.rc = rc
+
+
+_lib = None
+
+
+def lib():
+    """Load libmhd.so (built by ``__graft_entry__.build()``); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    L.mhd_config_default.argtypes = [ctypes.POINTER(Config), i32, i32, i32, i32]
+    L.mhd_config_default.restype = None
+    L.mhd_init.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(vp), ctypes.POINTER(Layout)]
+    L.mhd_finalize.argtypes = [vp]
+    L.mhd_finalize.restype = None
+    L.mhd_strerror.argtypes = [ctypes.c_int]
+    L.mhd_strerror.restype = ctypes.c_char_p
+    L.mhd_halo_periodic.argtypes = [vp, vp, vp]
+    L.mhd_rk3_substep.argtypes = [vp, i32, vp, vp, vp, vp, dbl, vp]
+    L.mhd_step.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(i32), vp, vp, dbl, i32, vp]
+    L.mhd_reduce.argtypes = [vp, vp, i32, i32, ctypes.POINTER(dbl), vp]
+    for fn in ("mhd_init", "mhd_halo_periodic", "mhd_rk3_substep", "mhd_step", "mhd_reduce"):
+        getattr(L, fn).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(fn, rc):
+    if rc != 0:
+        raise MhdError(fn, rc)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Solver:
+    """One context of the library on the current HIP device.
+
+    Buffers are flat torch tensors of ``layout.total_elems`` elements; use
+    :meth:`grid_view` / :meth:`interior_view` for (8, mz, my, mx) views.
+    """
+
+    def __init__(self, nx, ny, nz, precision="f64", **phys):
+        self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        cfg = Config()
+        lib().mhd_config_default(ctypes.byref(cfg), nx, ny, nz, self.precision)
+        for k, v in phys.items():
+            if k == "bext":
+                cfg.bext = (ctypes.c_double * 3)(*[float(b) for b in v])
+            elif k == "lengths":
+                cfg.lx, cfg.ly, cfg.lz = (float(x) for x in v)
+            else:
+                setattr(cfg, k, float(v))
+        self.cfg = cfg
+        self.layout = Layout()
+        self._ctx = ctypes.c_void_p()
+        _check("mhd_init", lib().mhd_init(ctypes.byref(cfg), ctypes.byref(self._ctx),
+                                          ctypes.byref(self.layout)))
+        self.n = (nx, ny, nz)
+
+    def close(self):
+        if self._ctx:
+            lib().mhd_finalize(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------- buffers
+    @property
+    def torch_dtype(self):
+        import torch
+        return torch.float64 if self.layout.elem_size == 8 else torch.float32
+
+    def empty(self):
+        import torch
+        return torch.empty(self.layout.total_elems, dtype=self.torch_dtype, device="cuda")
+
+    def zeros(self):
+        import torch
+        return torch.zeros(self.layout.total_elems, dtype=self.torch_dtype, device="cuda")
+
+    def grid_view(self, buf):
+        L = self.layout
+        return buf.as_strided((8, L.mz, L.my, L.mx), (L.field_stride, L.my * L.mx, L.mx, 1))
+
+    def interior_view(self, buf):
+        nx, ny, nz = self.n
+        return self.grid_view(buf)[:, 3:3 + nz, 3:3 + ny, 3:3 + nx]
+
+    def upload(self, fields: np.ndarray, buf=None, fill_halo=True):
+        """Copy an (8, nz, ny, nx) host array into the interior of a buffer
+        (converted to the storage type) and fill its periodic halo."""
+        import torch
+        buf = self.empty() if buf is None else buf
+        host = torch.from_numpy(np.ascontiguousarray(fields)).to(self.torch_dtype)
+        self.interior_view(buf).copy_(host)
+        if fill_halo:
+            self.halo_periodic(buf)
+        return buf
+
+    def download(self, buf) -> np.ndarray:
+        """Interior of a buffer as an (8, nz, ny, nx) float64 host array."""
+        return self.interior_view(buf).cpu().double().numpy()
+
+    # -------------------------------------------------------------- ABI
+    def halo_periodic(self, buf, stream=None):
+        _check("mhd_halo_periodic", lib().mhd_halo_periodic(self._ctx, _ptr(buf), _stream(stream)))
+
+    def rk3_substep(self, s, f_in, f_out, w, comp=None, dt=1e-3, stream=None):
+        _check("mhd_rk3_substep", lib().mhd_rk3_substep(self._ctx, s, _ptr(f_in), _ptr(f_out),
+                                                        _ptr(w), _ptr(comp), dt, _stream(stream)))
+
+    def step(self, f, cur, w, comp=None, dt=1e-3, nsteps=1, stream=None) -> int:
+        """nsteps RK3 steps starting from f[cur]; returns the result's index."""
+        arr = (ctypes.c_void_p * 2)(f[0].data_ptr(), f[1].data_ptr())
+        c = ctypes.c_int32(cur)
+        _check("mhd_step", lib().mhd_step(self._ctx, arr, ctypes.byref(c), _ptr(w), _ptr(comp),
+                                          dt, nsteps, _stream(stream)))
+        return c.value
+
+    def reduce(self, buf, field, op, stream=None) -> float:
+        q = FIELD_NAMES.index(field) if isinstance(field, str) else int(field)
+        out = ctypes.c_double()
+        _check("mhd_reduce", lib().mhd_reduce(self._ctx, _ptr(buf), q, RED_OPS[op],
+                                              ctypes.byref(out), _stream(stream)))
+        return out.value

@@ -1,0 +1,91 @@
+"""The C-ABI library loads on the CPU and exports every declared symbol;
+argument validation and the no-device path return the documented codes.
+No compute call is made here."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2103_01597_amd import mhd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared(header):
+    text = open(os.path.join(ROOT, "include", header)).read()
+    return sorted(set(re.findall(r"^\s*(?:void|int|const char)\s*\*?\s*(mhd\w*)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(mhd.LIB_PATH):
+        pytest.fail("libmhd.so is not built (run __graft_entry__.build())")
+    return mhd.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    declared = _declared("mhd.h")
+    assert set(declared) == set(mhd.EXPORTS)
+    out = subprocess.run(["nm", "-D", "--defined-only", mhd.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (\w+)$", out, re.M))
+    for name in declared:
+        assert name in exported, name
+        assert getattr(L, name) is not None
+
+
+def test_strerror_and_defaults(L):
+    assert L.mhd_strerror(0) == b"ok"
+    assert L.mhd_strerror(1) == b"invalid argument"
+    assert L.mhd_strerror(2) == b"no usable HIP device"
+    assert L.mhd_strerror(99) == b"unknown status"
+    cfg = mhd.Config()
+    L.mhd_config_default(ctypes.byref(cfg), 32, 16, 8, mhd.F32C)
+    assert (cfg.nx, cfg.ny, cfg.nz, cfg.precision) == (32, 16, 8, 1)
+    assert cfg.gamma == 5.0 / 3.0 and cfg.nu == 5e-3 and cfg.eta == 5e-3 and cfg.K == 5e-3
+    assert cfg.cs0 == 1.0 and cfg.cp == 1.0 and cfg.mu0 == 1.0 and cfg.zeta == 0.0
+    assert abs(cfg.lx - 6.283185307179586) < 1e-15 and list(cfg.bext) == [0.0, 0.0, 0.0]
+
+
+def _init(L, **kw):
+    cfg = mhd.Config()
+    L.mhd_config_default(ctypes.byref(cfg), 8, 8, 8, 0)
+    for k, v in kw.items():
+        setattr(cfg, k, v)
+    ctx = ctypes.c_void_p(12345)
+    lay = mhd.Layout()
+    rc = L.mhd_init(ctypes.byref(cfg), ctypes.byref(ctx), ctypes.byref(lay))
+    return rc, ctx
+
+
+@pytest.mark.parametrize("bad", [dict(nx=0), dict(ny=-3), dict(precision=3), dict(precision=-1),
+                                 dict(gamma=1.0), dict(cp=0.0), dict(mu0=0.0),
+                                 dict(lx=float("nan")), dict(lz=-1.0), dict(nu=float("inf")),
+                                 dict(nx=3000, ny=3000, nz=3000)])
+def test_init_rejects_invalid_config(L, bad):
+    rc, ctx = _init(L, **bad)
+    assert rc == 1
+    assert ctx.value is None  # *out is NULL on failure
+
+
+def test_null_arguments(L):
+    vp = ctypes.c_void_p
+    assert L.mhd_init(None, ctypes.byref(vp()), ctypes.byref(mhd.Layout())) == 1
+    assert L.mhd_halo_periodic(None, vp(1), None) == 1
+    assert L.mhd_rk3_substep(None, 0, vp(1), vp(2), vp(3), None, 1e-3, None) == 1
+    cur = ctypes.c_int32(0)
+    arr = (vp * 2)(1, 2)
+    assert L.mhd_step(None, arr, ctypes.byref(cur), vp(3), None, 1e-3, 1, None) == 1
+    out = ctypes.c_double()
+    assert L.mhd_reduce(None, vp(1), 0, 0, ctypes.byref(out), None) == 1
+    L.mhd_finalize(None)
+
+
+def test_no_device_path(L):
+    if os.environ.get("HIP_VISIBLE_DEVICES") is None and os.path.exists("/dev/kfd"):
+        pytest.skip("a GPU device node is present")
+    rc, ctx = _init(L)
+    assert rc == 2
+    assert ctx.value is None

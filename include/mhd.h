@@ -71,9 +71,17 @@ enum mhd_reduce_op {
 };
 
 /* ---------------------------------------------------------------- types */
+/* Which fused-substep kernel runs (same results up to rounding order). */
+enum mhd_kernel {
+    MHD_KERNEL_TILED = 0, /* LDS-tiled z-marching kernel (default) */
+    MHD_KERNEL_DIRECT = 1 /* one thread per cell, stencil read from global memory */
+};
+
 typedef struct mhd_config {
     int32_t nx, ny, nz;   /* computational domain n_i >= 1 (interior cells per axis) */
     int32_t precision;    /* enum mhd_precision */
+    int32_t kernel;       /* enum mhd_kernel */
+    int32_t reserved_;    /* must be 0 */
     double lx, ly, lz;    /* box lengths; h_i = l_i / n_i (vertex-centred cells) */
     /* Appendix B constants: adiabatic sound speed at ln rho = lnrho0, s = 0;
      * adiabatic index; heat capacity at constant pressure; reference ln rho;
@@ -103,14 +111,16 @@ typedef struct mhd_ctx mhd_ctx;
 
 /* Fill *cfg with the defaults for an n = (nx, ny, nz) grid: l = 2*pi per
  * axis, cs0 = 1, gamma = 5/3, cp = 1, lnrho0 = 0, mu0 = 1,
- * nu = eta = 5e-3, zeta = 0, K = 5e-3, bext = 0.  Never fails. */
+ * nu = eta = 5e-3, zeta = 0, K = 5e-3, bext = 0, kernel = MHD_KERNEL_TILED.
+ * Never fails. */
 void mhd_config_default(mhd_config *cfg, int32_t nx, int32_t ny, int32_t nz,
                         int32_t precision);
 
 /* Validate *cfg, bind the current HIP device and create a context.
  * Writes the buffer geometry to *layout.  *out stays NULL on failure.
- * Errors: MHD_ERR_INVALID (NULL argument, n_i < 1, non-finite or
- * non-positive lengths, gamma <= 1, cp <= 0, mu0 == 0, unknown precision),
+ * Errors: MHD_ERR_INVALID (NULL argument, n_i < 1, a padded field of more
+ * than 2^31 - 4096 cells, non-finite or non-positive lengths, gamma <= 1,
+ * cp <= 0, mu0 == 0, unknown precision or kernel, reserved_ != 0),
  * MHD_ERR_NO_DEVICE, MHD_ERR_DEVICE, MHD_ERR_NOMEM. */
 int mhd_init(const mhd_config *cfg, mhd_ctx **out, mhd_layout *layout);
 

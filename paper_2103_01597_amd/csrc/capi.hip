@@ -52,6 +52,8 @@ int validate(const mhd_config* c)
     if (!c) return MHD_ERR_INVALID;
     if (c->nx < 1 || c->ny < 1 || c->nz < 1) return MHD_ERR_INVALID;
     if (c->precision < MHD_F64 || c->precision > MHD_F32) return MHD_ERR_INVALID;
+    if (c->kernel != MHD_KERNEL_TILED && c->kernel != MHD_KERNEL_DIRECT) return MHD_ERR_INVALID;
+    if (c->reserved_ != 0) return MHD_ERR_INVALID;
     if (!finite_pos(c->lx) || !finite_pos(c->ly) || !finite_pos(c->lz)) return MHD_ERR_INVALID;
     if (!isfinite(c->gamma) || c->gamma <= 1.0) return MHD_ERR_INVALID;
     if (!finite_pos(c->cp) || !isfinite(c->cs0) || !isfinite(c->lnrho0)) return MHD_ERR_INVALID;
@@ -85,8 +87,10 @@ int one_substep(mhd_ctx* ctx, int s, const void* f_in, void* f_out, void* w, voi
                 double dt, hipStream_t st)
 {
     bool launched = false;
-    hipError_t e = launch_rk3_tiled(ctx->grid, ctx->phys, ctx->cfg.precision, s, f_in, f_out, w,
-                                    comp, dt, st, &launched);
+    hipError_t e = hipSuccess;
+    if (ctx->cfg.kernel == MHD_KERNEL_TILED)
+        e = launch_rk3_tiled(ctx->grid, ctx->phys, ctx->cfg.precision, s, f_in, f_out, w, comp, dt,
+                             st, &launched);
     if (e == hipSuccess && !launched)
         e = launch_rk3_direct(ctx->grid, ctx->phys, ctx->cfg.precision, s, f_in, f_out, w, comp,
                               dt, st);

@@ -63,6 +63,32 @@ __device__ __forceinline__ A derivm(const T* p, int sa, int sb)
     return A(CM_1) * e1 + A(CM_2) * e2 + A(CM_3) * e3;
 }
 
+// 2N update of one cell of one field with the old register value w_old
+// already loaded (ignored for s == 0: alpha_0 = 0, so w is never read).
+template <int PREC>
+__device__ __forceinline__ void rk_update_v(int s, typename Prec<PREC>::T f_in,
+                                            typename Prec<PREC>::T w_old,
+                                            typename Prec<PREC>::Rt rhs, double dt,
+                                            typename Prec<PREC>::T* w,
+                                            typename Prec<PREC>::T* f_out,
+                                            typename Prec<PREC>::T* comp)
+{
+    using T = typename Prec<PREC>::T;
+    using Rt = typename Prec<PREC>::Rt;
+    const Rt alpha = Rt(s == 1 ? RK_ALPHA[1] : RK_ALPHA[2]);
+    const Rt beta = Rt(s == 0 ? RK_BETA[0] : (s == 1 ? RK_BETA[1] : RK_BETA[2]));
+    const Rt dtr = Rt(dt);
+    const Rt wn = (s == 0) ? dtr * rhs : alpha * Rt(w_old) + dtr * rhs;
+    *w = T(wn);
+    if constexpr (PREC == MHD_F32C) {
+        float c = *comp;
+        *f_out = kahan_add(f_in, beta * wn, c);
+        *comp = c;
+    } else {
+        *f_out = T(f_in + beta * wn);
+    }
+}
+
 // 2N update of one cell of one field.  s == 0 never reads w (alpha_0 = 0).
 template <int PREC>
 __device__ __forceinline__ void rk_update(int s, typename Prec<PREC>::T f_in,
@@ -72,19 +98,7 @@ __device__ __forceinline__ void rk_update(int s, typename Prec<PREC>::T f_in,
                                           typename Prec<PREC>::T* comp)
 {
     using T = typename Prec<PREC>::T;
-    using Rt = typename Prec<PREC>::Rt;
-    const Rt alpha = Rt(s == 1 ? RK_ALPHA[1] : RK_ALPHA[2]);
-    const Rt beta = Rt(s == 0 ? RK_BETA[0] : (s == 1 ? RK_BETA[1] : RK_BETA[2]));
-    const Rt dtr = Rt(dt);
-    const Rt wn = (s == 0) ? dtr * rhs : alpha * Rt(*w) + dtr * rhs;
-    *w = T(wn);
-    if constexpr (PREC == MHD_F32C) {
-        float c = *comp;
-        *f_out = kahan_add(f_in, beta * wn, c);
-        *comp = c;
-    } else {
-        *f_out = T(f_in + beta * wn);
-    }
+    rk_update_v<PREC>(s, f_in, s == 0 ? T(0) : *w, rhs, dt, w, f_out, comp);
 }
 
 }  // namespace mhd

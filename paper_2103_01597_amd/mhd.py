@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libmhd.so")
 
 F64, F32C, F32 = 0, 1, 2
 PRECISIONS = {"f64": F64, "f32c": F32C, "f32": F32}
+KERNELS = {"tiled": 0, "direct": 1}
 RED_OPS = {"sum": 0, "sumsq": 1, "maxabs": 2, "min": 3, "max": 4, "sumexp": 5, "nonfinite": 6}
 FIELD_NAMES = ("lnrho", "ux", "uy", "uz", "ss", "ax", "ay", "az")
 STATUS = {0: "MHD_OK", 1: "MHD_ERR_INVALID", 2: "MHD_ERR_NO_DEVICE", 3: "MHD_ERR_DEVICE",
@@ -30,7 +31,8 @@ EXPORTS = ("mhd_config_default", "mhd_init", "mhd_finalize", "mhd_strerror",
 
 class Config(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
-                ("precision", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("kernel", ctypes.c_int32),
+                ("reserved_", ctypes.c_int32),
                 ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double),
                 ("cs0", ctypes.c_double), ("gamma", ctypes.c_double), ("cp", ctypes.c_double),
                 ("lnrho0", ctypes.c_double), ("mu0", ctypes.c_double), ("nu", ctypes.c_double),
@@ -100,10 +102,11 @@ class Solver:
     :meth:`grid_view` / :meth:`interior_view` for (8, mz, my, mx) views.
     """
 
-    def __init__(self, nx, ny, nz, precision="f64", **phys):
+    def __init__(self, nx, ny, nz, precision="f64", kernel="tiled", **phys):
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         cfg = Config()
         lib().mhd_config_default(ctypes.byref(cfg), nx, ny, nz, self.precision)
+        cfg.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
         for k, v in phys.items():
             if k == "bext":
                 cfg.bext = (ctypes.c_double * 3)(*[float(b) for b in v])

@@ -46,6 +46,7 @@ def test_strerror_and_defaults(L):
     assert (cfg.nx, cfg.ny, cfg.nz, cfg.precision) == (32, 16, 8, 1)
     assert cfg.gamma == 5.0 / 3.0 and cfg.nu == 5e-3 and cfg.eta == 5e-3 and cfg.K == 5e-3
     assert cfg.cs0 == 1.0 and cfg.cp == 1.0 and cfg.mu0 == 1.0 and cfg.zeta == 0.0
+    assert cfg.kernel == 0 and cfg.reserved_ == 0
     assert abs(cfg.lx - 6.283185307179586) < 1e-15 and list(cfg.bext) == [0.0, 0.0, 0.0]
 
 
@@ -63,7 +64,8 @@ def _init(L, **kw):
 @pytest.mark.parametrize("bad", [dict(nx=0), dict(ny=-3), dict(precision=3), dict(precision=-1),
                                  dict(gamma=1.0), dict(cp=0.0), dict(mu0=0.0),
                                  dict(lx=float("nan")), dict(lz=-1.0), dict(nu=float("inf")),
-                                 dict(nx=3000, ny=3000, nz=3000)])
+                                 dict(nx=3000, ny=3000, nz=3000), dict(kernel=2),
+                                 dict(reserved_=1)])
 def test_init_rejects_invalid_config(L, bad):
     rc, ctx = _init(L, **bad)
     assert rc == 1

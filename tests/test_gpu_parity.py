@@ -39,9 +39,12 @@ def _errs(got, ref):
     return [oracle.rel_err(got[q], ref[q]) for q in range(8)]
 
 
-def _run_steps(mhd, f0, p, dt, nsteps, prec="f64"):
+KERNELS = ["tiled", "direct"]
+
+
+def _run_steps(mhd, f0, p, dt, nsteps, prec="f64", kernel="tiled"):
     import torch
-    S = mhd.Solver(p.nx, p.ny, p.nz, prec, **_phys_kw(p))
+    S = mhd.Solver(p.nx, p.ny, p.nz, prec, kernel, **_phys_kw(p))
     a = S.upload(f0)
     b = S.empty()
     b.fill_(float("nan"))
@@ -74,16 +77,17 @@ def test_halo_fill_bitwise(mhd, shape, prec):
     assert np.array_equal(got, ref)
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("s", [0, 1, 2])
-def test_single_substep_parity(mhd, s):
+def test_single_substep_parity(mhd, s, kernel):
     import torch
     wl = inputs.WORKLOADS["oracle32"]
     n = wl["shape"]
-    say(f"substep s={s} {n}")
+    say(f"substep s={s} {n} {kernel}")
     p = oracle.Params(*n)
     f0 = inputs.workload_state("oracle32")
     w0 = inputs.fourier_modes(n, 3, 1e-5, seed=101)
-    S = mhd.Solver(*n, "f64", **_phys_kw(p))
+    S = mhd.Solver(*n, "f64", kernel, **_phys_kw(p))
     fin = S.upload(f0)
     fout = S.empty()
     fout.fill_(float("nan"))
@@ -104,12 +108,13 @@ def test_single_substep_parity(mhd, s):
     assert np.all(np.isnan(g[:, mask]))
 
 
-def test_full_step_oracle32(mhd):
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_full_step_oracle32(mhd, kernel):
     wl = inputs.WORKLOADS["oracle32"]
-    say(f"full step oracle32 {wl['shape']}")
+    say(f"full step oracle32 {wl['shape']} {kernel}")
     p = oracle.Params(*wl["shape"])
     f0 = inputs.workload_state("oracle32")
-    got = _run_steps(mhd, f0, p, wl["dt"], 1)
+    got = _run_steps(mhd, f0, p, wl["dt"], 1, kernel=kernel)
     ref = oracle.step(f0, wl["dt"], p, 1)
     e = _errs(got, ref)
     u = oracle.ulps(got, ref)
@@ -119,15 +124,16 @@ def test_full_step_oracle32(mhd):
 
 
 @pytest.mark.parametrize("shape", [(48, 40, 32), (37, 29, 31), (5, 7, 6), (64, 3, 2), (1, 1, 1),
-                                   (130, 9, 12)])
-def test_full_step_ragged_sizes(mhd, shape):
-    say(f"full step {shape}")
+                                   (130, 9, 12), (33, 17, 3)])
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_full_step_ragged_sizes(mhd, shape, kernel):
+    say(f"full step {shape} {kernel}")
     p = oracle.Params(*shape, lx=2 * math.pi * shape[0] / 32, ly=2 * math.pi * shape[1] / 32,
                       lz=2 * math.pi * shape[2] / 32, nu=0.02, eta=0.01, K=0.01, zeta=0.003,
                       bext=(0.02, -0.01, 0.03))
     f0 = inputs.fourier_modes(shape, 3, 0.05, seed=7,
                               lengths=(p.lx, p.ly, p.lz))
-    got = _run_steps(mhd, f0, p, 2e-3, 2)
+    got = _run_steps(mhd, f0, p, 2e-3, 2, kernel=kernel)
     ref = oracle.step(f0, 2e-3, p, 2)
     e = _errs(got, ref)
     say("  rel err:", ["%.2e" % x for x in e])
@@ -160,28 +166,29 @@ def test_graph_replay_equals_launches(mhd):
     assert cur == 0
 
 
-def test_bitwise_deterministic(mhd):
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_bitwise_deterministic(mhd, kernel):
     n = (40, 36, 33)
     f0 = inputs.fourier_modes(n, 4, 1e-2, seed=9)
     p = oracle.Params(*n)
-    r1 = _run_steps(mhd, f0, p, 1e-3, 2)
-    r2 = _run_steps(mhd, f0, p, 1e-3, 2)
+    r1 = _run_steps(mhd, f0, p, 1e-3, 2, kernel=kernel)
+    r2 = _run_steps(mhd, f0, p, 1e-3, 2, kernel=kernel)
     assert np.array_equal(r1, r2)
 
 
-def _sampled_step_check(mhd, wl_name, prec="f64", ncells=1500, seed=0):
+def _sampled_step_check(mhd, wl_name, prec="f64", ncells=1500, seed=0, kernel="tiled"):
     """One full step at full size; every substep's outputs are checked at
     sampled cells against the oracle evaluated one cell at a time on the
     GPU's own substep input."""
     import torch
     wl = inputs.WORKLOADS[wl_name]
     n = wl["shape"]
-    say(f"sampled full-size step {wl_name} {n} {prec}")
+    say(f"sampled full-size step {wl_name} {n} {prec} {kernel}")
     p = oracle.Params(*n, lx=wl.get("lengths", (2 * math.pi,) * 3)[0],
                       ly=wl.get("lengths", (2 * math.pi,) * 3)[1],
                       lz=wl.get("lengths", (2 * math.pi,) * 3)[2])
     f0 = inputs.workload_state(wl_name)
-    S = mhd.Solver(*n, prec, **_phys_kw(p))
+    S = mhd.Solver(*n, prec, kernel, **_phys_kw(p))
     bufs = [S.upload(f0), S.empty()]
     w = S.empty()
     rng = np.random.default_rng(seed)
@@ -214,8 +221,9 @@ def _sampled_step_check(mhd, wl_name, prec="f64", ncells=1500, seed=0):
     return worst
 
 
-def test_full_size_256_sampled(mhd):
-    assert _sampled_step_check(mhd, "sub256") <= TOL_F64
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_full_size_256_sampled(mhd, kernel):
+    assert _sampled_step_check(mhd, "sub256", kernel=kernel) <= TOL_F64
 
 
 def test_full_size_512_sampled(mhd):

@@ -23,10 +23,24 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+DEFAULT_KERNEL = "split"
+KERNEL_SOURCE = {"split": "rk3_split.hip", "tiled": "rk3_tiled.hip", "direct": "rk3_direct.hip"}
+KERNEL_SYMBOL = {"split": "k_rk3_split", "tiled": "k_rk3_tiled", "direct": "k_rk3_direct"}
+
+WORKLOAD_TEXT = {
+    "prec512": "prec512: 512^3 periodic, 8 fields, 1e-2 x 4 Fourier modes |k|<=8 seed 3, "
+               "dt 1e-3, halo fill every substep",
+    "sub256": "sub256: 256^3 periodic, 8 fields, 1e-2 x 4 Fourier modes |k|<=8 seed 2, "
+              "dt 1e-3, halo fill every substep",
+    "large1024x512x512": "large: 1024x512x512 periodic (4pi x 2pi x 2pi), u modes |k|<=16 "
+                         "amp 0.1, A amp 1e-3, seed 4, dt 1e-3, halo fill every substep",
+}
 
 # Compulsory HBM bytes per interior cell of the fused substep (8 fields):
 # read f_in, write w and f_out, plus read w for s > 0; F32C also reads and
@@ -38,13 +52,12 @@ BYTES_PER_CELL = {
 }
 
 
-def run_precision(mhd, inputs, torch, wl, prec, steps, warmup):
+def run_precision(mhd, inputs, torch, name, prec, steps, warmup, kernel):
+    wl = inputs.WORKLOADS[name]
     n = wl["shape"]
     cells = n[0] * n[1] * n[2]
-    S = mhd.Solver(*n, prec, lengths=wl.get("lengths", (2 * math.pi,) * 3))
-    host =inputs.fourier_modes(n, wl["kmax"], wl["amp"], wl["seed"])
-    bufs = [S.upload(host), S.empty()]
-    del host
+    S = mhd.Solver(*n, prec, kernel, lengths=wl.get("lengths", (2 * math.pi,) * 3))
+    bufs = [S.upload_fields(inputs.workload_fields(name)), S.empty()]
     w = S.zeros()
     comp = S.zeros() if prec == "f32c" else None
     dt = wl["dt"]
@@ -91,11 +104,42 @@ def run_precision(mhd, inputs, torch, wl, prec, steps, warmup):
     return res
 
 
-def cpu_baseline(inputs, wl):
-    """The oracle as it stands, one RK3 step on a 128^3 grid of the same
+def kernel_source_hash(kernel):
+    """SHA-256 of the sources a fused kernel is built from (its own file and
+    the headers it shares)."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2103_01597_amd", "csrc")
+    for name in (KERNEL_SOURCE[kernel], "rk3_common.hpp", "mhd_internal.hpp"):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, prec, workload):
+    """HBM bytes per launch of the fused kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on
+    a copy kernel of known size), or None when there is none or the kernel's
+    sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{KERNEL_SYMBOL[kernel]}_{prec}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_sha256") != kernel_source_hash(kernel):
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
+def cpu_baseline(inputs, wl, n1=256):
+    """The oracle as it stands, one RK3 step on an n1^3 grid of the same
     workload recipe (a bounded sample: about 10-30 s of host work)."""
     import oracle
-    n = (128, 128, 128)
+    n = (n1, n1, n1)
     f = inputs.fourier_modes(n, wl["kmax"], wl["amp"], wl["seed"])
     p = oracle.Params(*n)
     t = time.perf_counter()
@@ -104,7 +148,7 @@ def cpu_baseline(inputs, wl):
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return dict(value=3 * n[0] * n[1] * n[2] / dt / 1e9, unit="GCUPS", cores=threads,
                 kind="oracle",
-                sample=f"one RK3 step (3 substeps) of the FP64 oracle on 128^3 with the "
+                sample=f"one RK3 step (3 substeps) of the FP64 oracle on {n1}^3 with the "
                        f"same 8-field Fourier-mode recipe, {dt:.1f} s")
 
 
@@ -114,8 +158,16 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precisions", default="f64,f32c")
+    ap.add_argument("--precisions", default=None,
+                    help="comma list of f64, f32c, f32 (default: f64,f32c; f32c for "
+                         "the large workload)")
+    ap.add_argument("--workload", default="prec512",
+                    choices=["prec512", "sub256", "large1024x512x512"])
+    ap.add_argument("--kernel", default=DEFAULT_KERNEL, choices=["split", "tiled", "direct"],
+                    help="fused-substep kernel (default: %(default)s)")
     args = ap.parse_args()
+    if args.precisions is None:
+        args.precisions = "f32c" if args.workload == "large1024x512x512" else "f64,f32c"
     if args.gpus != 1:
         print("bench.py: this path is one GPU's share of the domain and has no multi-GPU "
               "mode; run with --gpus 1", file=sys.stderr)
@@ -125,16 +177,18 @@ def main():
     from paper_2103_01597_amd import inputs, mhd
     mhd.lib()
     torch.cuda.set_device(0)
-    wl = inputs.WORKLOADS["prec512"]
+    wl = inputs.WORKLOADS[args.workload]
     results = {}
     for prec in args.precisions.split(","):
-        results[prec] = run_precision(mhd, inputs, torch, wl, prec, args.steps, args.warmup)
+        results[prec] = run_precision(mhd, inputs, torch, args.workload, prec, args.steps,
+                                      args.warmup, args.kernel)
         print(f"# {prec}: {json.dumps(results[prec])}", file=sys.stderr, flush=True)
 
     main_prec = "f64" if "f64" in results else next(iter(results))
     r = results[main_prec]
     line = {
-        "metric": "GCUPS per RK3 substep at 512^3 (FP64; FP32-storage compensated beside it)",
+        "metric": "GCUPS per RK3 substep at 512^3 (FP64; FP32-storage compensated beside it)"
+                  if args.workload == "prec512" else f"GCUPS per RK3 substep ({args.workload})",
         "value": round(r["gcups"], 4),
         "unit": "GCUPS",
         "n_gpus": 1,
@@ -146,13 +200,13 @@ def main():
         "vs_baseline": None,
         "dtype": main_prec,
         "data": "synthetic",
-        "config": {"workload": "prec512: 512^3 periodic, 8 fields, 1e-2 x 4 Fourier modes "
-                               "|k|<=8 seed 3, dt 1e-3, halo fill every substep",
-                   "grid": [512, 512, 512], "precision": main_prec},
+        "config": {"workload": WORKLOAD_TEXT[args.workload], "grid": list(wl["shape"]),
+                   "precision": main_prec, "kernel": args.kernel},
         "roofline": {"bound": "hbm", "achieved": round(r["kernel_gbs"], 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(r["kernel_gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "fused RHS+RK3 substep",
+                     "frac": round(r["kernel_gbs"] / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(args.kernel, main_prec, args.workload),
+                     "kernel": KERNEL_SYMBOL[args.kernel],
                      "kernel_ms_avg": round(r["kernel_ms_avg"], 4)},
     }
     for prec, rr in results.items():
@@ -161,7 +215,7 @@ def main():
             line[f"{prec}_roofline_frac"] = round(rr["kernel_gbs"] / HBM_PEAK_GBS, 4)
             line[f"{prec}_kernel_ms_avg"] = round(rr["kernel_ms_avg"], 4)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(inputs, wl)
+        line["cpu_baseline"] = cpu_baseline(inputs, inputs.WORKLOADS["prec512"])
     print(json.dumps(line), flush=True)
 
 

@@ -73,8 +73,10 @@ enum mhd_reduce_op {
 /* ---------------------------------------------------------------- types */
 /* Which fused-substep kernel runs (same results up to rounding order). */
 enum mhd_kernel {
-    MHD_KERNEL_TILED = 0, /* LDS-tiled z-marching kernel (default) */
-    MHD_KERNEL_DIRECT = 1 /* one thread per cell, stencil read from global memory */
+    MHD_KERNEL_TILED = 0,  /* LDS-tiled z-marching kernel (default) */
+    MHD_KERNEL_DIRECT = 1, /* one thread per cell, stencil read from global memory */
+    MHD_KERNEL_SPLIT = 2   /* LDS-tiled z-march, two threads per cell splitting the
+                              fields (velocity side / entropy-induction side) */
 };
 
 typedef struct mhd_config {

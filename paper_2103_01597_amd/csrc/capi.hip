@@ -16,6 +16,9 @@ hipError_t launch_rk3_direct(const Grid& g, const Phys& P, int precision, int s,
 hipError_t launch_rk3_tiled(const Grid& g, const Phys& P, int precision, int s,
                             const void* f_in, void* f_out, void* w, void* comp, double dt,
                             hipStream_t st, bool* launched);
+hipError_t launch_rk3_split(const Grid& g, const Phys& P, const Phys* P_dev, int precision,
+                            int s, const void* f_in, void* f_out, void* w, void* comp, double dt,
+                            hipStream_t st);
 }  // namespace mhd
 
 using namespace mhd;
@@ -35,6 +38,7 @@ struct mhd_ctx {
     mhd_layout lay;
     Grid grid;
     Phys phys;
+    Phys* phys_dev;        // device copy of phys (read by the split kernel)
     int device;
     double* red_partials;  // device, REDUCE_BLOCKS doubles, then 1 result
     double* red_host;      // pinned host, 1 double
@@ -52,7 +56,9 @@ int validate(const mhd_config* c)
     if (!c) return MHD_ERR_INVALID;
     if (c->nx < 1 || c->ny < 1 || c->nz < 1) return MHD_ERR_INVALID;
     if (c->precision < MHD_F64 || c->precision > MHD_F32) return MHD_ERR_INVALID;
-    if (c->kernel != MHD_KERNEL_TILED && c->kernel != MHD_KERNEL_DIRECT) return MHD_ERR_INVALID;
+    if (c->kernel != MHD_KERNEL_TILED && c->kernel != MHD_KERNEL_DIRECT &&
+        c->kernel != MHD_KERNEL_SPLIT)
+        return MHD_ERR_INVALID;
     if (c->reserved_ != 0) return MHD_ERR_INVALID;
     if (!finite_pos(c->lx) || !finite_pos(c->ly) || !finite_pos(c->lz)) return MHD_ERR_INVALID;
     if (!isfinite(c->gamma) || c->gamma <= 1.0) return MHD_ERR_INVALID;
@@ -66,6 +72,9 @@ int validate(const mhd_config* c)
     // every padded field must be addressable with 32-bit offsets
     const int64_t mx = c->nx + 6, my = c->ny + 6, mz = c->nz + 6;
     if (mx * my * mz > (int64_t)INT32_MAX - 4096) return MHD_ERR_INVALID;
+    // and every padded field must be byte-addressable with 32-bit offsets
+    const int64_t elem = c->precision == MHD_F64 ? 8 : 4;
+    if ((mx * my * mz + 64) * elem > ((int64_t)1 << 32) - 65536) return MHD_ERR_INVALID;
     if (c->nz > 65535 || c->ny > 65535) return MHD_ERR_INVALID;
     return MHD_OK;
 }
@@ -88,9 +97,14 @@ int one_substep(mhd_ctx* ctx, int s, const void* f_in, void* f_out, void* w, voi
 {
     bool launched = false;
     hipError_t e = hipSuccess;
-    if (ctx->cfg.kernel == MHD_KERNEL_TILED)
+    if (ctx->cfg.kernel == MHD_KERNEL_TILED) {
         e = launch_rk3_tiled(ctx->grid, ctx->phys, ctx->cfg.precision, s, f_in, f_out, w, comp, dt,
                              st, &launched);
+    } else if (ctx->cfg.kernel == MHD_KERNEL_SPLIT) {
+        e = launch_rk3_split(ctx->grid, ctx->phys, ctx->phys_dev, ctx->cfg.precision, s, f_in,
+                             f_out, w, comp, dt, st);
+        launched = true;
+    }
     if (e == hipSuccess && !launched)
         e = launch_rk3_direct(ctx->grid, ctx->phys, ctx->cfg.precision, s, f_in, f_out, w, comp,
                               dt, st);
@@ -152,6 +166,12 @@ int ensure_graph(mhd_ctx* ctx, void* const f[2], int cur, void* w, void* comp, d
 }
 
 }  // namespace
+
+namespace mhd {
+// Read-only access to a context's geometry for the closure kernels.
+const Grid* ctx_grid(const mhd_ctx* ctx) { return &ctx->grid; }
+int ctx_precision(const mhd_ctx* ctx) { return ctx->cfg.precision; }
+}  // namespace mhd
 
 extern "C" {
 
@@ -247,6 +267,8 @@ int mhd_init(const mhd_config* cfg, mhd_ctx** out, mhd_layout* layout)
     P.cp_gm1 = cfg->cp * (cfg->gamma - 1.0);
 
     hipError_t e = hipMalloc(&ctx->red_partials, (REDUCE_BLOCKS + 1) * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&ctx->phys_dev, sizeof(Phys));
+    if (e == hipSuccess) e = hipMemcpy(ctx->phys_dev, &ctx->phys, sizeof(Phys), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipHostMalloc(&ctx->red_host, sizeof(double), hipHostMallocDefault);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -267,6 +289,7 @@ void mhd_finalize(mhd_ctx* ctx)
     for (auto& gr : ctx->graphs) drop_graph(gr);
     if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     if (ctx->red_partials) (void)hipFree(ctx->red_partials);
+    if (ctx->phys_dev) (void)hipFree(ctx->phys_dev);
     if (ctx->red_host) (void)hipHostFree(ctx->red_host);
     delete ctx;
 }

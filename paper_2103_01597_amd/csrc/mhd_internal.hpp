@@ -58,44 +58,64 @@ struct Derivs {
     Rt lapA[3], jmu[3];                // lap A and mu0*j = grad(div A) - lap A
 };
 
-// Right-hand side of Eqs. B.1-B.4 (H = C = 0, K constant) with the ideal
+// The right-hand side of Eqs. B.1-B.4 (H = C = 0, K constant) with the ideal
 // gas closure cs^2 = cs0^2 exp(gamma s/cp + (gamma-1)(lnrho - lnrho0)),
 // cp (gamma-1) T = cs^2; B = curl A + B_ext; S the traceless rate of shear.
+// It is assembled from four pieces so that a kernel may split the work
+// between the velocity side (B.1, B.2) and the entropy/induction side
+// (B.3, B.4); rhs_physics chains them.
+
+// Traceless rate of shear S, div u and S:S from the velocity gradient.
 template <typename Rt>
-__device__ __forceinline__ void rhs_physics(const Derivs<Rt>& d, const Phys& P, Rt out[NQ])
+__device__ __forceinline__ void shear(const Rt gu[3][3], Rt S[3][3], Rt& divu, Rt& SS)
 {
-    const Rt gamma = Rt(P.gamma), inv_cp = Rt(P.inv_cp), gm1 = Rt(P.gamma_m1);
-    const Rt nu = Rt(P.nu), zeta = Rt(P.zeta), eta = Rt(P.eta);
-    const Rt u[3] = {d.ux, d.uy, d.uz};
-
-    const Rt inv_rho = exp(-d.lnrho);
-    const Rt cs2 = Rt(P.cs0sq) * exp(gamma * d.ss * inv_cp + gm1 * (d.lnrho - Rt(P.lnrho0)));
-    const Rt inv_T = Rt(P.cp_gm1) / cs2;
-
-    const Rt divu = d.gu[0][0] + d.gu[1][1] + d.gu[2][2];
-    Rt S[3][3];
+    divu = gu[0][0] + gu[1][1] + gu[2][2];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b)
-            S[a][b] = Rt(0.5) * (d.gu[a][b] + d.gu[b][a]);
+            S[a][b] = Rt(0.5) * (gu[a][b] + gu[b][a]);
     const Rt third_divu = divu * Rt(1.0 / 3.0);
     S[0][0] -= third_divu;
     S[1][1] -= third_divu;
     S[2][2] -= third_divu;
+    SS = Rt(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            SS += S[a][b] * S[a][b];
+}
 
-    const Rt B[3] = {d.dAz_dy - d.dAy_dz + Rt(P.bext[0]),
-                     d.dAx_dz - d.dAz_dx + Rt(P.bext[1]),
-                     d.dAy_dx - d.dAx_dy + Rt(P.bext[2])};
+// B = curl A + B_ext, J = j (current density) and the Lorentz force j x B.
+template <typename Rt>
+__device__ __forceinline__ void magnetic(const Derivs<Rt>& d, const Phys& P, Rt B[3], Rt J[3],
+                                         Rt jxB[3])
+{
+    B[0] = d.dAz_dy - d.dAy_dz + Rt(P.bext[0]);
+    B[1] = d.dAx_dz - d.dAz_dx + Rt(P.bext[1]);
+    B[2] = d.dAy_dx - d.dAx_dy + Rt(P.bext[2]);
     const Rt inv_mu0 = Rt(P.inv_mu0);
-    const Rt J[3] = {d.jmu[0] * inv_mu0, d.jmu[1] * inv_mu0, d.jmu[2] * inv_mu0};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) J[a] = d.jmu[a] * inv_mu0;
+    jxB[0] = J[1] * B[2] - J[2] * B[1];
+    jxB[1] = J[2] * B[0] - J[0] * B[2];
+    jxB[2] = J[0] * B[1] - J[1] * B[0];
+}
 
-    // B.1
+// Eqs. B.1 and B.2: out[0] = d lnrho/dt, out[1..3] = du/dt.  Reads lnrho,
+// ss, u, gl, gs, gu, lapu, gdu of d.
+template <typename Rt>
+__device__ __forceinline__ void rhs_flow(const Derivs<Rt>& d, const Phys& P, const Rt S[3][3],
+                                         Rt divu, const Rt jxB[3], Rt out[4])
+{
+    const Rt gamma = Rt(P.gamma), inv_cp = Rt(P.inv_cp), gm1 = Rt(P.gamma_m1);
+    const Rt nu = Rt(P.nu), zeta = Rt(P.zeta);
+    const Rt u[3] = {d.ux, d.uy, d.uz};
+    const Rt inv_rho = exp(-d.lnrho);
+    const Rt cs2 = Rt(P.cs0sq) * exp(gamma * d.ss * inv_cp + gm1 * (d.lnrho - Rt(P.lnrho0)));
+
     out[0] = -(u[0] * d.gl[0] + u[1] * d.gl[1] + u[2] * d.gl[2]) - divu;
-
-    // B.2
-    const Rt jxB[3] = {J[1] * B[2] - J[2] * B[1], J[2] * B[0] - J[0] * B[2],
-                       J[0] * B[1] - J[1] * B[0]};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const Rt adv = u[0] * d.gu[a][0] + u[1] * d.gu[a][1] + u[2] * d.gu[a][2];
@@ -104,27 +124,48 @@ __device__ __forceinline__ void rhs_physics(const Derivs<Rt>& d, const Phys& P, 
         const Rt visc = nu * (d.lapu[a] + d.gdu[a] * Rt(1.0 / 3.0) + Rt(2) * Sgl);
         out[1 + a] = -adv + pres + jxB[a] * inv_rho + visc + zeta * d.gdu[a];
     }
+}
 
-    // B.3 divided by rho*T
-    Rt glnT2 = Rt(0), SS = Rt(0);
+// Eq. B.3 divided by rho*T (out[0] = ds/dt) and Eq. B.4 (out[1..3] =
+// dA/dt).  Reads lnrho, ss, u, gl, gs, lapl, laps, lapA of d.
+template <typename Rt>
+__device__ __forceinline__ void rhs_entropy_induction(const Derivs<Rt>& d, const Phys& P,
+                                                      Rt divu, Rt SS, const Rt B[3],
+                                                      const Rt J[3], Rt out[4])
+{
+    const Rt gamma = Rt(P.gamma), inv_cp = Rt(P.inv_cp), gm1 = Rt(P.gamma_m1);
+    const Rt nu = Rt(P.nu), zeta = Rt(P.zeta), eta = Rt(P.eta);
+    const Rt u[3] = {d.ux, d.uy, d.uz};
+    const Rt inv_rho = exp(-d.lnrho);
+    const Rt cs2 = Rt(P.cs0sq) * exp(gamma * d.ss * inv_cp + gm1 * (d.lnrho - Rt(P.lnrho0)));
+    const Rt inv_T = Rt(P.cp_gm1) / cs2;
+
+    Rt glnT2 = Rt(0);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const Rt g = gamma * d.gs[a] * inv_cp + gm1 * d.gl[a];
         glnT2 += g * g;
-#pragma unroll
-        for (int b = 0; b < 3; ++b)
-            SS += S[a][b] * S[a][b];
     }
     const Rt laplnT = gamma * d.laps * inv_cp + gm1 * d.lapl;
     const Rt jj = J[0] * J[0] + J[1] * J[1] + J[2] * J[2];
     const Rt udgs = u[0] * d.gs[0] + u[1] * d.gs[1] + u[2] * d.gs[2];
-    out[4] = -udgs + Rt(P.K) * inv_rho * (laplnT + glnT2) +
+    out[0] = -udgs + Rt(P.K) * inv_rho * (laplnT + glnT2) +
              inv_T * (eta * Rt(P.mu0) * jj * inv_rho + Rt(2) * nu * SS + zeta * divu * divu);
 
-    // B.4
-    out[5] = u[1] * B[2] - u[2] * B[1] + eta * d.lapA[0];
-    out[6] = u[2] * B[0] - u[0] * B[2] + eta * d.lapA[1];
-    out[7] = u[0] * B[1] - u[1] * B[0] + eta * d.lapA[2];
+    out[1] = u[1] * B[2] - u[2] * B[1] + eta * d.lapA[0];
+    out[2] = u[2] * B[0] - u[0] * B[2] + eta * d.lapA[1];
+    out[3] = u[0] * B[1] - u[1] * B[0] + eta * d.lapA[2];
+}
+
+// All of Eqs. B.1-B.4 at one cell: out[q] = d f_q / dt in field order.
+template <typename Rt>
+__device__ __forceinline__ void rhs_physics(const Derivs<Rt>& d, const Phys& P, Rt out[NQ])
+{
+    Rt S[3][3], divu, SS, B[3], J[3], jxB[3];
+    shear(d.gu, S, divu, SS);
+    magnetic(d, P, B, J, jxB);
+    rhs_flow(d, P, S, divu, jxB, out);
+    rhs_entropy_induction(d, P, divu, SS, B, J, out + 4);
 }
 
 // Kahan-compensated addition f <- f + y with running compensation c

@@ -1,0 +1,628 @@
+// Learned-closure kernels for gfx950 (declared in include/mhdnn.h).
+//
+// Periodic 3x3x3 convolutions run as implicit GEMMs on the BF16 matrix
+// cores (v_mfma_f32_32x32x16_bf16, FP32 accumulation):
+//   * forward / data gradient: M = cells, N = output channels (padded to
+//     32), K = 27 taps x input channels.  A block stages its 128-cell tile's
+//     neighbourhood (3 planes x (R+2) full periodic rows, channels last) and
+//     the weights in LDS; each wave owns 32 cells.  An A fragment is 8
+//     consecutive channels of one shifted cell (one 16-byte LDS read); a B
+//     fragment is 8 consecutive input channels of one weight row.
+//   * weight gradient: M = output channels, N = input channels (or 4 taps x
+//     8 channels for 8-channel inputs), K = cells.  Over one full periodic
+//     x-row, sum_x dz(x) x(x + dx) = sum_q dz(q - dx) x(q), so the x shift is
+//     moved onto three pre-shifted LDS copies of the dz tile and every
+//     fragment is 8 consecutive, 16-byte aligned cells of one channel.
+//     Per-block partial sums go to a workspace that a second kernel reduces
+//     in a fixed order (deterministic).
+// MFMA lane layout (32x32x16): lane l holds A row l%32 and B column l%32 at
+// K = 8(l/32)..8(l/32)+7; accumulator r of lane l is D[8(r/4) + 4(l/32) +
+// r%4][l%32].
+#include "mhd_internal.hpp"
+#include "../../include/mhdnn.h"
+
+namespace mhd {
+
+const Grid* ctx_grid(const mhd_ctx* ctx);
+int ctx_precision(const mhd_ctx* ctx);
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// Round-to-nearest-even FP32 -> BF16 (NaN stays NaN).
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float gelu(float v) { return 0.5f * v * (1.0f + erff(v * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float v)
+{
+    return 0.5f * (1.0f + erff(v * 0.70710678118654752f)) +
+           v * __expf(-0.5f * v * v) * 0.39894228040143268f;
+}
+
+__device__ __forceinline__ bf16x8 frag(const uint16_t* p)  // 16-byte aligned
+{
+    return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(p));
+}
+
+constexpr int TILE = 128;   // cells per conv tile
+constexpr int NTHR = 256;
+
+// ------------------------------------------------------------------ conv
+// MODE 0: hidden layer (z, GELU(z) as BF16); 1: output layer (FP32);
+// 2: data gradient (times GELU'(zprev), BF16).
+template <int CIN, int MODE>
+__global__ __launch_bounds__(NTHR) void k_conv(const uint16_t* __restrict__ x,
+                                               const uint16_t* __restrict__ w,
+                                               const float* __restrict__ bias,
+                                               const uint16_t* __restrict__ zprev, int n, int logn,
+                                               int batch, int cout, uint16_t* __restrict__ out0,
+                                               uint16_t* __restrict__ out1, float* __restrict__ outf)
+{
+    extern __shared__ __align__(16) uint16_t sm[];
+    const int R = TILE >> logn;              // full rows per tile
+    uint16_t* lw = sm;                       // [32][27][CIN]
+    uint16_t* lx = sm + 32 * 27 * CIN;       // [3][R+2][n][CIN]
+    const int n3 = n * n * n, tiles_per = n3 / TILE, tiles = tiles_per * batch;
+    const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63, h = l >> 5, col = l & 31;
+
+    for (int i = tid; i < 32 * 27 * CIN / 8; i += NTHR)
+        reinterpret_cast<u16x8*>(lw)[i] = reinterpret_cast<const u16x8*>(w)[i];
+
+    for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const int b = tile / tiles_per, c0 = (tile - b * tiles_per) * TILE;
+        const int k = c0 >> (2 * logn), j0 = (c0 >> logn) & (n - 1);
+        const uint16_t* xb = x + (size_t)b * n3 * CIN;
+        __syncthreads();  // previous tile's reads of lx are done (and lw is staged)
+        const int vecs = 3 * (R + 2) * n * CIN / 8;
+        for (int i = tid; i < vecs; i += NTHR) {
+            const int e = i * 8;                  // element index in lx
+            const int cell = e / CIN, ch = e - cell * CIN;
+            const int xx = cell & (n - 1), rp = cell >> logn;
+            const int r = rp % (R + 2), p = rp / (R + 2);
+            const int zz = (k - 1 + p + n) & (n - 1), yy = (j0 - 1 + r + n) & (n - 1);
+            const int src = (((zz << logn) + yy) << logn) + xx;
+            reinterpret_cast<u16x8*>(lx)[i] =
+                *reinterpret_cast<const u16x8*>(xb + (size_t)src * CIN + ch);
+        }
+        __syncthreads();
+
+        const int m = 32 * wv + col;             // this lane's A-row cell within the tile
+        const int rr = m >> logn, xx = m & (n - 1);
+        floatx16 acc = {};
+        if constexpr (CIN == 32) {
+#pragma unroll 3
+            for (int t = 0; t < 27; ++t) {
+                const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+                const int s = ((dz + 1) * (R + 2) + rr + dy + 1) * n + ((xx + dx) & (n - 1));
+#pragma unroll
+                for (int ch = 0; ch < 2; ++ch) {
+                    const bf16x8 a = frag(lx + s * 32 + 16 * ch + 8 * h);
+                    const bf16x8 bb = frag(lw + (col * 27 + t) * 32 + 16 * ch + 8 * h);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, acc, 0, 0, 0);
+                }
+            }
+        } else {  // CIN == 8: taps 2u (lanes 0-31) and 2u+1 (lanes 32-63) share one K chunk
+#pragma unroll 2
+            for (int u = 0; u < 14; ++u) {
+                const int t = 2 * u + h;
+                bf16x8 a = {}, bb = {};
+                if (t < 27) {
+                    const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+                    const int s = ((dz + 1) * (R + 2) + rr + dy + 1) * n + ((xx + dx) & (n - 1));
+                    a = frag(lx + s * 8);
+                    bb = frag(lw + (col * 27 + t) * 8);
+                }
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, acc, 0, 0, 0);
+            }
+        }
+
+        if (col < cout) {
+            const float bv = (MODE == 2) ? 0.0f : bias[col];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int cl = 32 * wv + 8 * (r >> 2) + 4 * h + (r & 3);
+                const size_t o = ((size_t)b * n3 + c0 + cl) * cout + col;
+                const float v = acc[r] + bv;
+                if constexpr (MODE == 0) {
+                    out0[o] = f2bf(v);
+                    out1[o] = f2bf(gelu(v));
+                } else if constexpr (MODE == 1) {
+                    outf[o] = v;
+                } else {
+                    out0[o] = f2bf(v * gelu_grad(bf2f(zprev[o])));
+                }
+            }
+        }
+    }
+}
+
+// --------------------------------------------------------------- wgrad
+constexpr int WG_TILES = 16;  // 128-cell tiles per wgrad block
+
+template <int CIN, int COUT>
+__global__ __launch_bounds__(NTHR) void k_wgrad(const uint16_t* __restrict__ x,
+                                                const uint16_t* __restrict__ dz, int n, int logn,
+                                                int batch, float* __restrict__ ws,
+                                                float* __restrict__ wsb)
+{
+    extern __shared__ __align__(16) uint16_t sm[];
+    const int R = TILE >> logn;
+    uint16_t* xs = sm;                           // [CIN][3][R+2][n]
+    uint16_t* ds = sm + CIN * 3 * (R + 2) * n;   // [3 shifts][32][R][n]
+    __shared__ float bsum[NTHR];
+    const int n3 = n * n * n, tiles_per = n3 / TILE, tiles = tiles_per * batch;
+    const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63, h = l >> 5, col = l & 31;
+    // accumulator sets of this wave: taps t = wv + 4i (CIN 32) or tap groups
+    // g = wv + 4i (CIN 8: g = 3*dxi + gi, gi selects 4 of the 9 (dz, dy) pairs)
+    constexpr int NSET = CIN == 32 ? 7 : 3;
+    floatx16 acc[NSET];
+#pragma unroll
+    for (int i = 0; i < NSET; ++i) acc[i] = floatx16{};
+    float bpart = 0.0f;
+
+    for (int it = 0; it < WG_TILES; ++it) {
+        const int tile = blockIdx.x * WG_TILES + it;
+        if (tile >= tiles) break;  // uniform across the block
+        const int b = tile / tiles_per, c0 = (tile - b * tiles_per) * TILE;
+        const int k = c0 >> (2 * logn), j0 = (c0 >> logn) & (n - 1);
+        const uint16_t* xb = x + (size_t)b * n3 * CIN;
+        const uint16_t* db = dz + (size_t)b * n3 * COUT;
+        __syncthreads();
+        // x neighbourhood, transposed to channel-major rows
+        const int xcells = 3 * (R + 2) * n;
+        for (int i = tid; i < xcells * CIN / 8; i += NTHR) {
+            const int cell = i / (CIN / 8), cg = (i - cell * (CIN / 8)) * 8;
+            const int xx = cell & (n - 1), rp = cell >> logn;
+            const int r = rp % (R + 2), p = rp / (R + 2);
+            const int zz = (k - 1 + p + n) & (n - 1), yy = (j0 - 1 + r + n) & (n - 1);
+            const u16x8 v = *reinterpret_cast<const u16x8*>(
+                xb + (size_t)((((zz << logn) + yy) << logn) + xx) * CIN + cg);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) xs[(cg + q) * xcells + cell] = v[q];
+        }
+        // dz tile, transposed, in three copies shifted along x: copy s holds
+        // dz(q - (s - 1)) at position q
+        for (int i = tid; i < TILE * 32; i += NTHR) {
+            const int cell = i >> 5, o = i & 31;
+            const int xx = cell & (n - 1), rr = cell >> logn;
+            const uint16_t v = o < COUT ? db[(size_t)(c0 + cell) * COUT + o] : (uint16_t)0;
+#pragma unroll
+            for (int s = 0; s < 3; ++s) {
+                const int q = (xx + s - 1) & (n - 1);
+                ds[((s * 32 + o) * R + rr) * n + q] = v;
+            }
+        }
+        // bias partial: thread tid sums dz[.][tid & 31] over cells tid>>5, +8, ...
+        if ((tid & 31) < COUT)
+            for (int cell = tid >> 5; cell < TILE; cell += 8)
+                bpart += bf2f(db[(size_t)(c0 + cell) * COUT + (tid & 31)]);
+        __syncthreads();
+
+#pragma unroll
+        for (int si = 0; si < NSET; ++si) {
+            const int set = wv + 4 * si;
+            if (set >= 27 || (CIN == 8 && set >= 9)) break;  // uniform per wave
+            int dxs, dzv[4], dyv[4];
+            if constexpr (CIN == 32) {
+                dxs = set % 3;  // shift copy s = dx + 1
+                dzv[0] = set / 9 - 1;
+                dyv[0] = (set / 3) % 3 - 1;
+            } else {
+                dxs = set / 3;
+                const int gi = set % 3;  // (dz, dy) pairs 4gi .. 4gi+3 of 9
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int pr = 4 * gi + q;
+                    dzv[q] = pr / 3 - 1;
+                    dyv[q] = pr % 3 - 1;
+                }
+            }
+#pragma unroll 2
+            for (int kc = 0; kc < TILE / 16; ++kc) {
+                const int cell = kc * 16 + 8 * h;
+                const int rr = cell >> logn, xq = cell & (n - 1);
+                const bf16x8 a = frag(ds + ((dxs * 32 + col) * R + rr) * n + xq);
+                bf16x8 bb = {};
+                if constexpr (CIN == 32) {
+                    bb = frag(xs + ((col * 3 + dzv[0] + 1) * (R + 2) + rr + dyv[0] + 1) * n + xq);
+                } else {
+                    const int tg = col >> 3, c = col & 7, pr = 4 * (set % 3) + tg;
+                    if (pr < 9) {
+                        const int dzz = pr / 3 - 1, dyy = pr % 3 - 1;
+                        bb = frag(xs + ((c * 3 + dzz + 1) * (R + 2) + rr + dyy + 1) * n + xq);
+                    }
+                }
+                acc[si] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, acc[si], 0, 0, 0);
+            }
+        }
+    }
+
+    // ---- write this block's partial sums: ws[block][t][o][c]
+    float* wb = ws + (size_t)blockIdx.x * 27 * 32 * 32;
+#pragma unroll
+    for (int si = 0; si < NSET; ++si) {
+        const int set = wv + 4 * si;
+        if (set >= 27 || (CIN == 8 && set >= 9)) break;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int o = 8 * (r >> 2) + 4 * h + (r & 3);
+            int t, c;
+            if constexpr (CIN == 32) {
+                t = set;
+                c = col;
+            } else {
+                const int tg = col >> 3, pr = 4 * (set % 3) + tg;
+                if (pr >= 9) continue;
+                t = 9 * (pr / 3) + 3 * (pr % 3) + set / 3;
+                c = col & 7;
+            }
+            wb[(t * 32 + o) * 32 + c] = acc[si][r];
+        }
+    }
+    bsum[tid] = bpart;
+    __syncthreads();
+    if (tid < 32) {
+        float sacc = 0.0f;
+        for (int i = 0; i < 8; ++i) sacc += bsum[i * 32 + tid];
+        wsb[blockIdx.x * 32 + tid] = sacc;
+    }
+}
+
+__global__ __launch_bounds__(NTHR) void k_wgrad_reduce(const float* __restrict__ ws,
+                                                       const float* __restrict__ wsb, int nblocks,
+                                                       int cin, int cout, float* __restrict__ dw,
+                                                       float* __restrict__ dbias)
+{
+    const int i = blockIdx.x * NTHR + threadIdx.x;  // over cout*27*cin, then cout biases
+    const int nw = cout * 27 * cin;
+    if (i < nw) {
+        const int o = i / (27 * cin), rem = i - o * 27 * cin, t = rem / cin, c = rem - t * cin;
+        float s = 0.0f;
+        for (int b = 0; b < nblocks; ++b) s += ws[((size_t)b * 27 * 32 + t * 32 + o) * 32 + c];
+        dw[i] = s;
+    } else if (i < nw + cout) {
+        const int o = i - nw;
+        float s = 0.0f;
+        for (int b = 0; b < nblocks; ++b) s += wsb[b * 32 + o];
+        dbias[o] = s;
+    }
+}
+
+// ------------------------------------------------------------ elementwise
+__global__ void k_prepare_weights(const float* __restrict__ w, int cin, int cout,
+                                  uint16_t* __restrict__ wpad, uint16_t* __restrict__ wtpad)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 32 * 27 * cin) {  // wpad[o][t][c]
+        const int o = i / (27 * cin), rem = i - o * 27 * cin;
+        wpad[i] = o < cout ? f2bf(w[o * 27 * cin + rem]) : (uint16_t)0;
+    }
+    if (wtpad && i < 32 * 27 * cout) {  // wtpad[c][t][o] = w[o][26 - t][c]
+        const int c = i / (27 * cout), rem = i - c * 27 * cout, t = rem / cout, o = rem - t * cout;
+        wtpad[i] = c < cin ? f2bf(w[(o * 27 + (26 - t)) * cin + c]) : (uint16_t)0;
+    }
+}
+
+struct Vec8 {
+    float v[8];
+};
+
+__global__ void k_pack(const float* __restrict__ src, const float* __restrict__ sub,
+                       int64_t bstride, int64_t fstride,
+                       int64_t origin, int64_t row, int64_t plane, int n, int logn, int batch,
+                       Vec8 mean, Vec8 inv_std, uint16_t* __restrict__ out)
+{
+    const int64_t n3 = (int64_t)n * n * n;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n3 * batch) return;
+    const int64_t b = i / n3, cell = i - b * n3;
+    const int64_t xx = cell & (n - 1), yy = (cell >> logn) & (n - 1), zz = cell >> (2 * logn);
+    const int64_t o = b * bstride + origin + zz * plane + yy * row + xx;
+    u16x8 v;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        float f = src[o + q * fstride];
+        if (sub) f -= sub[o + q * fstride];
+        v[q] = f2bf((f - mean.v[q]) * inv_std.v[q]);
+    }
+    reinterpret_cast<u16x8*>(out)[i] = v;
+}
+
+__global__ void k_apply(Grid g, float* __restrict__ f, float* __restrict__ comp,
+                        const float* __restrict__ y, Vec8 scale)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;  // interior cell, x fastest
+    const int n3 = g.nx * g.ny * g.nz;
+    if (i >= n3) return;
+    const int xx = i % g.nx, yy = (i / g.nx) % g.ny, zz = i / (g.nx * g.ny);
+    const int c = g.interior + zz * g.mxy + yy * g.mx + xx;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int64_t o = q * g.fstride + c;
+        const float add = y[(int64_t)i * 8 + q] * scale.v[q];
+        if (comp) {
+            float cc = comp[o];
+            f[o] = kahan_add(f[o], add, cc);
+            comp[o] = cc;
+        } else {
+            f[o] = f[o] + add;
+        }
+    }
+}
+
+template <typename E>
+__global__ void k_box4(Grid g, const E* __restrict__ fine, float* __restrict__ coarse)
+{
+    const int nc = g.nx / 4;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nc3 = nc * nc * nc;
+    if (i >= nc3 * 8) return;
+    const int q = i / nc3, cell = i - q * nc3;
+    const int I = cell % nc, J = (cell / nc) % nc, K = cell / (nc * nc);
+    const E* f = fine + q * g.fstride + g.interior;
+    double s = 0.0;
+    for (int c = 0; c < 4; ++c)
+        for (int b = 0; b < 4; ++b)
+            for (int a = 0; a < 4; ++a)
+                s += (double)f[(4 * K + c) * g.mxy + (4 * J + b) * g.mx + 4 * I + a];
+    coarse[i] = (float)(s / 64.0);
+}
+
+__global__ __launch_bounds__(NTHR) void k_mse(const float* __restrict__ y,
+                                              const float* __restrict__ t, int64_t count,
+                                              uint16_t* __restrict__ dy, float* __restrict__ part)
+{
+    __shared__ float sh[NTHR];
+    const float scale = 2.0f / (float)count, inv = 1.0f / (float)count;
+    float acc = 0.0f;
+    for (int64_t i = (int64_t)blockIdx.x * NTHR + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * NTHR) {
+        const float d = y[i] - t[i];
+        dy[i] = f2bf(scale * d);
+        acc += d * d * inv;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int hh = NTHR / 2; hh > 0; hh >>= 1) {
+        if (threadIdx.x < hh) sh[threadIdx.x] += sh[threadIdx.x + hh];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
+                       float c1, float c2)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+int ilog2(int n)
+{
+    int l = 0;
+    while ((1 << l) < n) ++l;
+    return (1 << l) == n ? l : -1;
+}
+
+bool conv_n_ok(int n) { return n == 16 || n == 32 || n == 64; }
+
+int status(hipError_t e) { return e == hipSuccess ? MHD_OK : MHD_ERR_DEVICE; }
+
+size_t conv_lds(int cin, int n) { return 2 * (32 * 27 * cin + 3 * (TILE / n + 2) * n * cin); }
+size_t wgrad_lds(int cin, int n) { return 2 * (cin * 3 * (TILE / n + 2) * n + 3 * 32 * TILE); }
+
+template <int CIN, int MODE>
+hipError_t launch_conv(const uint16_t* x, const uint16_t* w, const float* bias, const uint16_t* zp,
+                       int n, int batch, int cout, uint16_t* o0, uint16_t* o1, float* of,
+                       hipStream_t st)
+{
+    const size_t lds = conv_lds(CIN, n);
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_conv<CIN, MODE>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)conv_lds(CIN, 16) > (int)conv_lds(CIN, 64)
+                                               ? (int)conv_lds(CIN, 16) : (int)conv_lds(CIN, 64));
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const int tiles = n * n * n / TILE * batch;
+    const int grid = tiles < 1024 ? tiles : 1024;
+    hipLaunchKernelGGL((k_conv<CIN, MODE>), dim3(grid), dim3(NTHR), lds, st, x, w, bias, zp, n,
+                       ilog2(n), batch, cout, o0, o1, of);
+    return hipGetLastError();
+}
+
+template <int CIN, int COUT>
+hipError_t launch_wgrad(const uint16_t* x, const uint16_t* dz, int n, int batch, float* ws,
+                        float* dw, float* db, hipStream_t st)
+{
+    static bool attr = false;
+    if (!attr) {
+        const int m = (int)(wgrad_lds(CIN, 16) > wgrad_lds(CIN, 64) ? wgrad_lds(CIN, 16)
+                                                                     : wgrad_lds(CIN, 64));
+        hipError_t e = hipFuncSetAttribute((const void*)k_wgrad<CIN, COUT>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, m);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const int tiles = n * n * n / TILE * batch;
+    const int blocks = (tiles + WG_TILES - 1) / WG_TILES;
+    float* wsb = ws + (size_t)blocks * 27 * 32 * 32;
+    hipLaunchKernelGGL((k_wgrad<CIN, COUT>), dim3(blocks), dim3(NTHR), wgrad_lds(CIN, n), st, x,
+                       dz, n, ilog2(n), batch, ws, wsb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int total = COUT * 27 * CIN + COUT;
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((total + NTHR - 1) / NTHR), dim3(NTHR), 0, st, ws, wsb,
+                       blocks, CIN, COUT, dw, db);
+    return hipGetLastError();
+}
+
+}  // namespace
+}  // namespace mhd
+
+using namespace mhd;
+
+extern "C" {
+
+int mhdnn_box_filter4(const void* fine_ctx, const void* fine_fields, float* coarse, void* stream)
+{
+    if (!fine_ctx || !fine_fields || !coarse) return MHD_ERR_INVALID;
+    const mhd_ctx* ctx = (const mhd_ctx*)fine_ctx;
+    const Grid g = *ctx_grid(ctx);
+    if (g.nx != g.ny || g.nx != g.nz || g.nx % 4 != 0) return MHD_ERR_INVALID;
+    const int nc = g.nx / 4, total = nc * nc * nc * 8;
+    hipStream_t st = (hipStream_t)stream;
+    if (ctx_precision(ctx) == MHD_F64)
+        hipLaunchKernelGGL(k_box4<double>, dim3((total + 255) / 256), dim3(256), 0, st, g,
+                           (const double*)fine_fields, coarse);
+    else
+        hipLaunchKernelGGL(k_box4<float>, dim3((total + 255) / 256), dim3(256), 0, st, g,
+                           (const float*)fine_fields, coarse);
+    return status(hipGetLastError());
+}
+
+int mhdnn_pack(const float* src, const float* sub, int64_t batch_stride, int64_t field_stride,
+               int64_t origin, int64_t row, int64_t plane, int32_t n, int32_t batch,
+               const float* mean, const float* inv_std, uint16_t* x_bf16, void* stream)
+{
+    if (!src || !mean || !inv_std || !x_bf16 || batch < 1 || ilog2(n) < 0) return MHD_ERR_INVALID;
+    Vec8 mm, is;
+    for (int q = 0; q < 8; ++q) {
+        mm.v[q] = mean[q];
+        is.v[q] = inv_std[q];
+    }
+    const int64_t total = (int64_t)n * n * n * batch;
+    hipLaunchKernelGGL(k_pack, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)stream, src, sub, batch_stride, field_stride, origin, row, plane, n,
+                       ilog2(n), batch, mm, is, x_bf16);
+    return status(hipGetLastError());
+}
+
+int mhdnn_conv3d_fwd(const uint16_t* x, const uint16_t* w_pad, const float* bias, int32_t n,
+                     int32_t batch, int32_t cin, int32_t cout, int32_t mode, uint16_t* z_bf16,
+                     uint16_t* a_bf16, float* y_f32, void* stream)
+{
+    if (!x || !w_pad || !bias || !conv_n_ok(n) || batch < 1) return MHD_ERR_INVALID;
+    if ((cin != 8 && cin != 32) || (cout != 8 && cout != 32)) return MHD_ERR_INVALID;
+    if (mode == 0 && (!z_bf16 || !a_bf16)) return MHD_ERR_INVALID;
+    if (mode == 1 && !y_f32) return MHD_ERR_INVALID;
+    if (mode != 0 && mode != 1) return MHD_ERR_INVALID;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    if (mode == 0)
+        e = cin == 32 ? launch_conv<32, 0>(x, w_pad, bias, nullptr, n, batch, cout, z_bf16, a_bf16,
+                                           nullptr, st)
+                      : launch_conv<8, 0>(x, w_pad, bias, nullptr, n, batch, cout, z_bf16, a_bf16,
+                                          nullptr, st);
+    else
+        e = cin == 32 ? launch_conv<32, 1>(x, w_pad, bias, nullptr, n, batch, cout, nullptr,
+                                           nullptr, y_f32, st)
+                      : launch_conv<8, 1>(x, w_pad, bias, nullptr, n, batch, cout, nullptr,
+                                          nullptr, y_f32, st);
+    return status(e);
+}
+
+int mhdnn_conv3d_dgrad(const uint16_t* dz, const uint16_t* wt_pad, const uint16_t* zprev,
+                       int32_t n, int32_t batch, int32_t cin_dz, int32_t cprev, uint16_t* dprev,
+                       void* stream)
+{
+    if (!dz || !wt_pad || !zprev || !dprev || !conv_n_ok(n) || batch < 1) return MHD_ERR_INVALID;
+    if ((cin_dz != 8 && cin_dz != 32) || (cprev != 8 && cprev != 32)) return MHD_ERR_INVALID;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = cin_dz == 32
+                       ? launch_conv<32, 2>(dz, wt_pad, nullptr, zprev, n, batch, cprev, dprev,
+                                            nullptr, nullptr, st)
+                       : launch_conv<8, 2>(dz, wt_pad, nullptr, zprev, n, batch, cprev, dprev,
+                                           nullptr, nullptr, st);
+    return status(e);
+}
+
+int64_t mhdnn_wgrad_workspace_floats(int32_t n, int32_t batch)
+{
+    if (!conv_n_ok(n) || batch < 1) return 0;
+    const int64_t tiles = (int64_t)n * n * n / TILE * batch;
+    const int64_t blocks = (tiles + WG_TILES - 1) / WG_TILES;
+    return blocks * (27 * 32 * 32 + 32);
+}
+
+int mhdnn_conv3d_wgrad(const uint16_t* x, const uint16_t* dz, int32_t n, int32_t batch,
+                       int32_t cin, int32_t cout, float* workspace, float* dw, float* db,
+                       void* stream)
+{
+    if (!x || !dz || !workspace || !dw || !db || !conv_n_ok(n) || batch < 1) return MHD_ERR_INVALID;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    if (cin == 8 && cout == 32) e = launch_wgrad<8, 32>(x, dz, n, batch, workspace, dw, db, st);
+    else if (cin == 32 && cout == 32) e = launch_wgrad<32, 32>(x, dz, n, batch, workspace, dw, db, st);
+    else if (cin == 32 && cout == 8) e = launch_wgrad<32, 8>(x, dz, n, batch, workspace, dw, db, st);
+    else if (cin == 8 && cout == 8) e = launch_wgrad<8, 8>(x, dz, n, batch, workspace, dw, db, st);
+    else return MHD_ERR_INVALID;
+    return status(e);
+}
+
+int mhdnn_prepare_weights(const float* w, int32_t cin, int32_t cout, uint16_t* w_pad,
+                          uint16_t* wt_pad, void* stream)
+{
+    if (!w || !w_pad || (cin != 8 && cin != 32) || (cout != 8 && cout != 32)) return MHD_ERR_INVALID;
+    const int total = 32 * 27 * 32;
+    hipLaunchKernelGGL(k_prepare_weights, dim3((total + 255) / 256), dim3(256), 0,
+                       (hipStream_t)stream, w, cin, cout, w_pad, wt_pad);
+    return status(hipGetLastError());
+}
+
+int mhdnn_mse(const float* y, const float* target, int64_t count, uint16_t* dy_bf16,
+              float* loss_partials, void* stream)
+{
+    if (!y || !target || !dy_bf16 || !loss_partials || count < 1) return MHD_ERR_INVALID;
+    hipLaunchKernelGGL(k_mse, dim3(256), dim3(NTHR), 0, (hipStream_t)stream, y, target, count,
+                       dy_bf16, loss_partials);
+    return status(hipGetLastError());
+}
+
+int mhdnn_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1,
+               float b2, float eps, int32_t t, void* stream)
+{
+    if (!p || !g || !m || !v || n < 0 || t < 1) return MHD_ERR_INVALID;
+    if (n == 0) return MHD_OK;
+    const float c1 = 1.0f - powf(b1, (float)t), c2 = 1.0f - powf(b2, (float)t);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)stream, p, g, m, v, n, lr, b1, b2, eps, c1, c2);
+    return status(hipGetLastError());
+}
+
+int mhdnn_apply(const void* ctx_, void* fields, void* comp, const float* y, const float* scale,
+                void* stream)
+{
+    if (!ctx_ || !fields || !y || !scale) return MHD_ERR_INVALID;
+    const mhd_ctx* ctx = (const mhd_ctx*)ctx_;
+    if (ctx_precision(ctx) == MHD_F64) return MHD_ERR_INVALID;
+    const Grid g = *ctx_grid(ctx);
+    Vec8 sc;
+    for (int q = 0; q < 8; ++q) sc.v[q] = scale[q];
+    const int n3 = g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(k_apply, dim3((n3 + 255) / 256), dim3(256), 0, (hipStream_t)stream, g,
+                       (float*)fields, (float*)comp, y, sc);
+    return status(hipGetLastError());
+}
+
+}  // extern "C"

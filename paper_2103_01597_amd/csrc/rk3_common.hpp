@@ -63,6 +63,31 @@ __device__ __forceinline__ A derivm(const T* p, int sa, int sb)
     return A(CM_1) * e1 + A(CM_2) * e2 + A(CM_3) * e3;
 }
 
+// 2N update of one cell of one field, by value: returns the new register
+// value and the new state (and, for the compensated FP32 variant, updates the
+// compensation c).  w_old is ignored for s == 0 (alpha_0 = 0).
+template <int PREC>
+__device__ __forceinline__ void rk_values(int s, typename Prec<PREC>::T f_in,
+                                          typename Prec<PREC>::T w_old,
+                                          typename Prec<PREC>::Rt rhs, double dt,
+                                          typename Prec<PREC>::T& w_new,
+                                          typename Prec<PREC>::T& f_new,
+                                          typename Prec<PREC>::T& c)
+{
+    using T = typename Prec<PREC>::T;
+    using Rt = typename Prec<PREC>::Rt;
+    const Rt alpha = Rt(s == 1 ? RK_ALPHA[1] : RK_ALPHA[2]);
+    const Rt beta = Rt(s == 0 ? RK_BETA[0] : (s == 1 ? RK_BETA[1] : RK_BETA[2]));
+    const Rt dtr = Rt(dt);
+    const Rt wn = (s == 0) ? dtr * rhs : alpha * Rt(w_old) + dtr * rhs;
+    w_new = T(wn);
+    if constexpr (PREC == MHD_F32C) {
+        f_new = kahan_add(f_in, beta * wn, c);
+    } else {
+        f_new = T(f_in + beta * wn);
+    }
+}
+
 // 2N update of one cell of one field with the old register value w_old
 // already loaded (ignored for s == 0: alpha_0 = 0, so w is never read).
 template <int PREC>

@@ -1,0 +1,535 @@
+// Fused RHS + RK3 substep, LDS-tiled z-marching kernel with two wave groups
+// per cell (gfx950).
+//
+// The data flow is that of the single-group tiled kernel -- a 32 x 8 column
+// tile marched through z, an LDS ring of 4 halo'd planes (t .. t+3) of all
+// 8 fields, a 3-deep register history of the own column, the xz / yz mixed
+// derivatives split into a future half read from the ring and a carried
+// past half -- but each cell is served by two threads in different waves:
+//   group F (waves 0-3): lnrho, ux, uy, uz -- their derivatives, Eq. B.1
+//                        and Eq. B.2, and their 2N updates;
+//   group M (waves 4-7): ss, Ax, Ay, Az -- their derivatives, Eqs. B.3 and
+//                        B.4, and their 2N updates.
+// Each group loads, stores and differentiates only its own four fields.
+// After the derivative phase the groups swap what the other side's
+// equations need through LDS:
+//   F -> M (10 values): lnrho, u, grad lnrho, lap lnrho, S:S, div u;
+//   M -> F (7 values):  ss, grad s, j x B.
+// With 512 threads per workgroup the FP64 ring (136 KB) still fits one
+// workgroup per CU, so every SIMD runs two waves instead of one; a wave
+// hides the LDS and barrier latency of the other.  The F -> M values live
+// in LDS past the ring; the M -> F values reuse the slot of plane t once
+// every wave has finished reading it.
+#include <type_traits>
+
+#include "mhd_internal.hpp"
+#include "rk3_common.hpp"
+
+namespace mhd {
+namespace {
+
+constexpr int TX = 32, TY = 8, NC = TX * TY;  // cells per tile plane
+constexpr int NTH = 2 * NC;                    // threads: two groups of NC
+constexpr int HX = TX + 2 * R, HY = TY + 2 * R, PLANE = HX * HY;  // 38 x 14 = 532
+constexpr int SLOT = NQ * PLANE;
+constexpr int NSLOT = 4;
+constexpr int FULL = PLANE / NC;   // plane elements per field every thread of a group loads
+constexpr int EXTRA = PLANE % NC;  // threads that load one more
+constexpr int NXF = 10;            // values F hands to M
+constexpr int NXM = 7;             // values M hands to F
+
+template <int PREC>
+constexpr size_t ring_bytes() { return sizeof(typename Prec<PREC>::T) * NSLOT * SLOT; }
+template <int PREC>
+constexpr size_t lds_bytes() { return ring_bytes<PREC>() + sizeof(typename Prec<PREC>::Rt) * NXF * NC; }
+
+static_assert(sizeof(double) * NXM * NC <= sizeof(double) * SLOT, "M->F values must fit one slot");
+static_assert(NC % 64 == 0, "each group must be whole waves");
+
+struct TileMap {
+    int ntx, nty;
+    int round;  // workgroups resident at once (0: plain order)
+};
+
+// Per-axis scale factors of the integer-weight stencils.
+struct Scales {
+    double d1[3];   // 1/(60 h_a)
+    double d2[3];   // 1/(180 h_a^2)
+    double mxy;     // 1/(720 h_x h_y)
+    double wxz[3];  // {270, -27, 2}/(720 h_x h_z)
+    double wyz[3];  // {270, -27, 2}/(720 h_y h_z)
+};
+
+constexpr int NO_TILE = -1;
+
+// Workgroup b -> tile, XCD-aware: within a round of `round` resident
+// workgroups, XCD k (which receives every 8th workgroup) gets a contiguous
+// run of tiles, so tiles sharing an L2 are spatial neighbours.
+__device__ __forceinline__ int tile_of_block(int b, const TileMap& m)
+{
+    const int tiles = m.ntx * m.nty;
+    if (m.round <= 0 || (m.round & 7) != 0) return b < tiles ? b : NO_TILE;
+    const int r = b / m.round, w = b - r * m.round;
+    const int rem = min(tiles - r * m.round, m.round);
+    const int per = (rem + 7) >> 3;
+    const int k = w >> 3;
+    if (k >= per) return NO_TILE;
+    const int t = r * m.round + (w & 7) * per + k;
+    return t < r * m.round + rem ? t : NO_TILE;
+}
+
+template <int PREC>
+__global__ __launch_bounds__(NTH, 1) void k_rk3_split(Grid g, const Phys* P_dev, Scales sc, TileMap map, int s,
+                                                     const typename Prec<PREC>::T* __restrict__ fin,
+                                                     typename Prec<PREC>::T* __restrict__ fout,
+                                                     typename Prec<PREC>::T* __restrict__ w,
+                                                     typename Prec<PREC>::T* __restrict__ comp,
+                                                     double dt)
+{
+    using T = typename Prec<PREC>::T;
+    using Rt = typename Prec<PREC>::Rt;
+    using D2 = typename Prec<PREC>::D2;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* __restrict__ lds = reinterpret_cast<T*>(smem_raw);
+    Rt* __restrict__ xf = reinterpret_cast<Rt*>(smem_raw + ring_bytes<PREC>());  // [NXF][NC]
+
+    const int tile = tile_of_block(blockIdx.x, map);
+    if (tile == NO_TILE) return;  // the whole workgroup exits together
+    const int tx = tile % map.ntx, ty = tile / map.ntx;
+    const int x0 = tx * TX, y0 = ty * TY;
+    // group index, made visibly wave-uniform so that the two groups' code
+    // paths (each with its own registers and the same barriers) are scalar
+    // branches
+    const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x / NC);
+    const int tid = threadIdx.x - grp * NC, lx = tid % TX, ly = tid / TX;
+    const bool active = (x0 + lx < g.nx) && (y0 + ly < g.ny);
+    const bool extra = tid < EXTRA;
+
+    auto field_ptr = [&](auto* base, int q) { return base + q * g.fstride; };
+    auto at = [](auto* p, unsigned idx) {
+        using Pt = decltype(p);
+        using C = typename std::conditional<std::is_const<typename std::remove_pointer<Pt>::type>::value,
+                                            const char*, char*>::type;
+        return reinterpret_cast<Pt>(reinterpret_cast<C>(p) + idx * (unsigned)sizeof(T));
+    };
+
+    // The whole march runs in one of two instantiations, one per group, so
+    // that each group's registers are allocated for its own path only.  Both
+    // execute the same sequence of barriers.
+    auto march = [&](auto group_tag) {
+        constexpr int G = decltype(group_tag)::value;
+        // ---- per-thread load slots of the halo'd tile plane (clamped into the
+        // padded grid for ragged tiles); each group loads its own four fields
+        constexpr int q0 = 4 * G;  // first of the group's fields
+        constexpr int NLOAD = FULL + (EXTRA > 0 ? 1 : 0);
+        unsigned goff[NLOAD];
+#pragma unroll
+        for (int k = 0; k < NLOAD; ++k) {
+            const int e = min(tid + k * NC, PLANE - 1);
+            const int r = e / HX, c = e - r * HX;
+            const int px = min(x0 + c, g.mx - 1), py = min(y0 + r, g.my - 1);
+            goff[k] = (unsigned)(py * g.mx + px);
+        }
+
+        T pre[4][NLOAD];
+        auto load_plane = [&](int t) {
+            const unsigned zo = (unsigned)((t + R) * g.mxy);
+#pragma unroll
+            for (int k4 = 0; k4 < 4; ++k4) {
+                const T* f = field_ptr(fin, q0 + k4);
+#pragma unroll
+                for (int k = 0; k < FULL; ++k) pre[k4][k] = *at(f, goff[k] + zo);
+            }
+            if constexpr (EXTRA > 0) {
+                if (extra) {
+#pragma unroll
+                    for (int k4 = 0; k4 < 4; ++k4) pre[k4][FULL] = *at(field_ptr(fin, q0 + k4), goff[FULL] + zo);
+                }
+            }
+        };
+        auto store_plane = [&](int slot) {
+            T* base = lds + slot * SLOT + q0 * PLANE + tid;
+#pragma unroll
+            for (int k4 = 0; k4 < 4; ++k4)
+#pragma unroll
+                for (int k = 0; k < FULL; ++k) base[k4 * PLANE + k * NC] = pre[k4][k];
+            if constexpr (EXTRA > 0) {
+                if (extra) {
+#pragma unroll
+                    for (int k4 = 0; k4 < 4; ++k4) base[k4 * PLANE + FULL * NC] = pre[k4][FULL];
+                }
+            }
+        };
+
+        const int cofs = (ly + R) * HX + (lx + R);
+        auto V = [&](int slot, int q, int dy, int dx) -> T {
+            return lds[slot * SLOT + q * PLANE + cofs + dy * HX + dx];
+        };
+
+        // ---- z state of the group's fields: own-column history (t-3, t-2, t-1),
+        // indexed by field within the group, and the carried past halves of the
+        // group's three xz/yz mixed combinations:
+        //   F: 0 Dxz uz, 1 Dyz uz, 2 Dxz ux + Dyz uy
+        //   M: 0 Dxz Az, 1 Dyz Az, 2 Dxz Ax + Dyz Ay
+        T hist[3][4];
+        D2 past[3][3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) hist[k][q] = T(0);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) past[c][k] = D2(0);
+        T wold[4] = {}, wnew[4] = {}, fnew[4] = {}, cc[4] = {};
+
+        auto cell_index = [&](int t) { return g.interior + t * g.mxy + (y0 + ly) * g.mx + (x0 + lx); };
+
+        constexpr int SOFS = 8;
+        load_plane(-3);
+        for (int t = -7; t < g.nz; ++t) {
+            const bool out = t >= 0;  // uniform: warm-up planes only feed the z state
+            const int s0 = (t + SOFS) & 3;
+            if (t >= -3) {
+                const int s1 = (t + 1 + SOFS) & 3, s2 = (t + 2 + SOFS) & 3, s3 = (t + 3 + SOFS) & 3;
+                const int sl[4] = {s0, s1, s2, s3};
+
+                auto sum2 = [&](int q, int dir, int m) {
+                    return dir == 0 ? D2(V(s0, q, 0, m)) + D2(V(s0, q, 0, -m))
+                                    : D2(V(s0, q, m, 0)) + D2(V(s0, q, -m, 0));
+                };
+                auto first = [&](int q, int dir) -> Rt {
+                    auto g1 = [&](int m) -> Rt {
+                        return dir == 0 ? Rt(V(s0, q, 0, m)) - Rt(V(s0, q, 0, -m))
+                                        : Rt(V(s0, q, m, 0)) - Rt(V(s0, q, -m, 0));
+                    };
+                    return (Rt(45) * g1(1) - Rt(9) * g1(2) + g1(3)) * Rt(sc.d1[dir]);
+                };
+                // own column of field q (group-local index k4), plane t+k, k = -3..3
+                auto col = [&](int q, int k4, int k) -> T {
+                    return k < 0 ? hist[k + 3][k4] : V(sl[k], q, 0, 0);
+                };
+                auto dz1 = [&](int q, int k4) -> Rt {
+                    return (Rt(45) * (Rt(col(q, k4, 1)) - Rt(col(q, k4, -1))) -
+                            Rt(9) * (Rt(col(q, k4, 2)) - Rt(col(q, k4, -2))) +
+                            (Rt(col(q, k4, 3)) - Rt(col(q, k4, -3)))) * Rt(sc.d1[2]);
+                };
+                auto second = [&](int q, int k4, D2& xx, D2& yy, D2& zz) {
+                    const D2 f0 = D2(-490) * D2(V(s0, q, 0, 0));
+                    xx = (D2(270) * sum2(q, 0, 1) - D2(27) * sum2(q, 0, 2) + D2(2) * sum2(q, 0, 3) + f0) *
+                         D2(sc.d2[0]);
+                    yy = (D2(270) * sum2(q, 1, 1) - D2(27) * sum2(q, 1, 2) + D2(2) * sum2(q, 1, 3) + f0) *
+                         D2(sc.d2[1]);
+                    zz = (D2(270) * (D2(col(q, k4, 1)) + D2(col(q, k4, -1))) -
+                          D2(27) * (D2(col(q, k4, 2)) + D2(col(q, k4, -2))) +
+                          D2(2) * (D2(col(q, k4, 3)) + D2(col(q, k4, -3))) + f0) * D2(sc.d2[2]);
+                };
+                auto dxy = [&](int q) -> D2 {
+                    auto e = [&](int m) {
+                        return (D2(V(s0, q, m, m)) + D2(V(s0, q, -m, -m))) -
+                               (D2(V(s0, q, -m, m)) + D2(V(s0, q, m, -m)));
+                    };
+                    return (D2(270) * e(1) - D2(27) * e(2) + D2(2) * e(3)) * D2(sc.mxy);
+                };
+                // xz (dir 0) / yz (dir 1) mixed derivative of field q for the
+                // group's combination cb; see the single-group tiled kernel.
+                auto mixed = [&](int q, int dir, int cb, bool first_of_combo) -> D2 {
+                    const double* wm = dir == 0 ? sc.wxz : sc.wyz;
+                    auto dd = [&](int slot, int m) {
+                        return dir == 0 ? D2(V(slot, q, 0, m)) - D2(V(slot, q, 0, -m))
+                                        : D2(V(slot, q, m, 0)) - D2(V(slot, q, -m, 0));
+                    };
+                    D2 res = D2(0);
+                    if (out) {
+                        res = D2(wm[0]) * dd(s1, 1) + D2(wm[1]) * dd(s2, 2) + D2(wm[2]) * dd(s3, 3);
+                        if (first_of_combo) res -= past[cb][0];
+                    }
+                    const D2 c1 = D2(wm[0]) * dd(s0, 1), c2 = D2(wm[1]) * dd(s0, 2),
+                             c3 = D2(wm[2]) * dd(s0, 3);
+                    if (first_of_combo) {
+                        past[cb][0] = past[cb][1] + c1;
+                        past[cb][1] = past[cb][2] + c2;
+                        past[cb][2] = c3;
+                    } else {
+                        past[cb][0] += c1;
+                        past[cb][1] += c2;
+                        past[cb][2] += c3;
+                    }
+                    return res;
+                };
+#define MHD_PHASE_FENCE() __builtin_amdgcn_sched_barrier(0)
+
+                Derivs<Rt> d;
+                if constexpr (G == 0) {
+                    // ================= group F: lnrho, ux, uy, uz
+                    D2 gdu[3] = {D2(0), D2(0), D2(0)};
+                    if (out) {
+                        d.lnrho = Rt(V(s0, 0, 0, 0));
+                        d.gl[0] = first(0, 0); d.gl[1] = first(0, 1); d.gl[2] = dz1(0, 0);
+                        D2 xx, yy, zz;
+                        second(0, 0, xx, yy, zz);
+                        d.lapl = Rt(xx + yy + zz);
+                    }
+                    MHD_PHASE_FENCE();
+                    {
+                        const D2 mz = mixed(1, 0, 2, true);
+                        if (out) {
+                            d.ux = Rt(V(s0, 1, 0, 0));
+                            d.gu[0][0] = first(1, 0); d.gu[0][1] = first(1, 1); d.gu[0][2] = dz1(1, 1);
+                            D2 xx, yy, zz;
+                            second(1, 1, xx, yy, zz);
+                            d.lapu[0] = Rt(xx + yy + zz);
+                            gdu[0] += xx;
+                            gdu[1] += dxy(1);
+                            gdu[2] += mz;
+                        }
+                    }
+                    MHD_PHASE_FENCE();
+                    {
+                        const D2 mz = mixed(2, 1, 2, false);
+                        if (out) {
+                            d.uy = Rt(V(s0, 2, 0, 0));
+                            d.gu[1][0] = first(2, 0); d.gu[1][1] = first(2, 1); d.gu[1][2] = dz1(2, 2);
+                            D2 xx, yy, zz;
+                            second(2, 2, xx, yy, zz);
+                            d.lapu[1] = Rt(xx + yy + zz);
+                            gdu[1] += yy;
+                            gdu[0] += dxy(2);
+                            gdu[2] += mz;
+                        }
+                    }
+                    MHD_PHASE_FENCE();
+                    {
+                        const D2 mx = mixed(3, 0, 0, true);
+                        const D2 my = mixed(3, 1, 1, true);
+                        if (out) {
+                            d.uz = Rt(V(s0, 3, 0, 0));
+                            d.gu[2][0] = first(3, 0); d.gu[2][1] = first(3, 1); d.gu[2][2] = dz1(3, 3);
+                            D2 xx, yy, zz;
+                            second(3, 3, xx, yy, zz);
+                            d.lapu[2] = Rt(xx + yy + zz);
+                            gdu[2] += zz;
+                            gdu[0] += mx;
+                            gdu[1] += my;
+                        }
+                    }
+                    MHD_PHASE_FENCE();
+                    if (out) {
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) d.gdu[a] = Rt(gdu[a]);
+                    }
+                } else {
+                    // ================= group M: ss, Ax, Ay, Az
+                    D2 jmu[3] = {D2(0), D2(0), D2(0)};
+                    if (out) {
+                        d.ss = Rt(V(s0, 4, 0, 0));
+                        d.gs[0] = first(4, 0); d.gs[1] = first(4, 1); d.gs[2] = dz1(4, 0);
+                        D2 xx, yy, zz;
+                        second(4, 0, xx, yy, zz);
+                        d.laps = Rt(xx + yy + zz);
+                    }
+                    MHD_PHASE_FENCE();
+                    {
+                        const D2 mz = mixed(5, 0, 2, true);
+                        if (out) {
+                            d.dAx_dy = first(5, 1);
+                            d.dAx_dz = dz1(5, 1);
+                            D2 xx, yy, zz;
+                            second(5, 1, xx, yy, zz);
+                            d.lapA[0] = Rt(xx + yy + zz);
+                            jmu[0] -= yy + zz;
+                            jmu[1] += dxy(5);
+                            jmu[2] += mz;
+                        }
+                    }
+                    MHD_PHASE_FENCE();
+                    {
+                        const D2 mz = mixed(6, 1, 2, false);
+                        if (out) {
+                            d.dAy_dx = first(6, 0);
+                            d.dAy_dz = dz1(6, 2);
+                            D2 xx, yy, zz;
+                            second(6, 2, xx, yy, zz);
+                            d.lapA[1] = Rt(xx + yy + zz);
+                            jmu[1] -= xx + zz;
+                            jmu[0] += dxy(6);
+                            jmu[2] += mz;
+                        }
+                    }
+                    MHD_PHASE_FENCE();
+                    {
+                        const D2 mx = mixed(7, 0, 0, true);
+                        const D2 my = mixed(7, 1, 1, true);
+                        if (out) {
+                            d.dAz_dx = first(7, 0);
+                            d.dAz_dy = first(7, 1);
+                            D2 xx, yy, zz;
+                            second(7, 3, xx, yy, zz);
+                            d.lapA[2] = Rt(xx + yy + zz);
+                            jmu[2] -= xx + yy;
+                            jmu[0] += mx;
+                            jmu[1] += my;
+                        }
+                    }
+                    MHD_PHASE_FENCE();
+                    if (out) {
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) d.jmu[a] = Rt(jmu[a]);
+                    }
+                }
+#undef MHD_PHASE_FENCE
+
+                // centre values of the group's fields (the 2N update's f_in) and
+                // the history shift, both before plane t's slot is reused
+                T fc[4];
+#pragma unroll
+                for (int k4 = 0; k4 < 4; ++k4) {
+                    fc[k4] = V(s0, q0 + k4, 0, 0);
+                    hist[0][k4] = hist[1][k4];
+                    hist[1][k4] = hist[2][k4];
+                    hist[2][k4] = fc[k4];
+                }
+
+                if (out) {
+                    // the physics constants are read here, per plane, from device
+                    // memory (scalar loads) rather than held in scalar registers
+                    // across the march, which would spill
+                    const Phys P = *P_dev;
+                    Rt S[3][3], divu = Rt(0), SS = Rt(0), B[3], J[3], jxB[3];
+                    if constexpr (G == 0) {
+                        shear(d.gu, S, divu, SS);
+                        const Rt v[NXF] = {d.lnrho, d.ux, d.uy, d.uz, d.gl[0], d.gl[1], d.gl[2],
+                                           d.lapl, SS, divu};
+#pragma unroll
+                        for (int i = 0; i < NXF; ++i) xf[i * NC + tid] = v[i];
+                    } else {
+                        magnetic(d, P, B, J, jxB);
+                    }
+                    __syncthreads();  // every read of plane t's slot is done
+                    Rt* __restrict__ xm = reinterpret_cast<Rt*>(lds + s0 * SLOT);  // [NXM][NC]
+                    if constexpr (G == 1) {
+                        const Rt v[NXM] = {d.ss, d.gs[0], d.gs[1], d.gs[2], jxB[0], jxB[1], jxB[2]};
+#pragma unroll
+                        for (int i = 0; i < NXM; ++i) xm[i * NC + tid] = v[i];
+                    }
+                    __syncthreads();  // exchanged values visible
+                    Rt rhs[4];
+                    if constexpr (G == 0) {
+                        d.ss = xm[0 * NC + tid];
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            d.gs[a] = xm[(1 + a) * NC + tid];
+                            jxB[a] = xm[(4 + a) * NC + tid];
+                        }
+                        rhs_flow(d, P, S, divu, jxB, rhs);
+                    } else {
+                        d.lnrho = xf[0 * NC + tid];
+                        d.ux = xf[1 * NC + tid];
+                        d.uy = xf[2 * NC + tid];
+                        d.uz = xf[3 * NC + tid];
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) d.gl[a] = xf[(4 + a) * NC + tid];
+                        d.lapl = xf[7 * NC + tid];
+                        SS = xf[8 * NC + tid];
+                        divu = xf[9 * NC + tid];
+                        rhs_entropy_induction(d, P, divu, SS, B, J, rhs);
+                    }
+#pragma unroll
+                    for (int k4 = 0; k4 < 4; ++k4)
+                        rk_values<PREC>(s, fc[k4], wold[k4], rhs[k4], dt, wnew[k4], fnew[k4], cc[k4]);
+                }
+            }
+
+            // ---- plane t+4 replaces plane t in the ring (after every read of the
+            // exchanged values in that slot); this plane's results go out; plane
+            // t+5 and the next plane's register values are fetched
+            __syncthreads();
+            store_plane((t + 4 + SOFS) & 3);
+            if (t >= 0 && active) {
+                const unsigned c = (unsigned)cell_index(t);
+#pragma unroll
+                for (int k4 = 0; k4 < 4; ++k4) {
+                    *at(field_ptr(w, q0 + k4), c) = wnew[k4];
+                    *at(field_ptr(fout, q0 + k4), c) = fnew[k4];
+                    if constexpr (PREC == MHD_F32C) *at(field_ptr(comp, q0 + k4), c) = cc[k4];
+                }
+            }
+            if (t + 5 <= g.nz + 2) load_plane(t + 5);
+            if (active && t + 1 >= 0 && t + 1 < g.nz) {
+                const unsigned c = (unsigned)cell_index(t + 1);
+                if (s > 0) {
+#pragma unroll
+                    for (int k4 = 0; k4 < 4; ++k4) wold[k4] = *at(field_ptr(w, q0 + k4), c);
+                }
+                if constexpr (PREC == MHD_F32C) {
+#pragma unroll
+                    for (int k4 = 0; k4 < 4; ++k4) cc[k4] = *at(field_ptr(comp, q0 + k4), c);
+                }
+            }
+            __syncthreads();  // plane t+4 visible to every wave
+        }
+    };
+    if (grp == 0)
+        march(std::integral_constant<int, 0>{});
+    else
+        march(std::integral_constant<int, 1>{});
+}
+
+template <int PREC>
+hipError_t launch_one(const Grid& g, const Phys& P, const Phys* P_dev, int s, const void* f_in,
+                      void* f_out, void* w, void* comp, double dt, hipStream_t st)
+{
+    using T = typename Prec<PREC>::T;
+    static int round = -1;  // resident workgroups per round on this device
+    const size_t lds = lds_bytes<PREC>();
+    if (round < 0) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_rk3_split<PREC>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        int per_cu = 0, dev = 0, cus = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rk3_split<PREC>, NTH, lds);
+        if (e != hipSuccess) return e;
+        e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        round = per_cu * cus;
+    }
+    TileMap m;
+    m.ntx = (g.nx + TX - 1) / TX;
+    m.nty = (g.ny + TY - 1) / TY;
+    m.round = round;
+    Scales sc;
+    for (int a = 0; a < 3; ++a) {
+        sc.d1[a] = P.inv_h[a] / 60.0;
+        sc.d2[a] = P.inv_h[a] * P.inv_h[a] / 180.0;
+    }
+    sc.mxy = P.inv_h[0] * P.inv_h[1] / 720.0;
+    const double wm[3] = {270.0, -27.0, 2.0};
+    for (int k = 0; k < 3; ++k) {
+        sc.wxz[k] = wm[k] * P.inv_h[0] * P.inv_h[2] / 720.0;
+        sc.wyz[k] = wm[k] * P.inv_h[1] * P.inv_h[2] / 720.0;
+    }
+    const int tiles = m.ntx * m.nty;
+    const int blocks = (round > 0 && (round & 7) == 0) ? (tiles + round - 1) / round * round : tiles;
+    hipLaunchKernelGGL(k_rk3_split<PREC>, dim3(blocks), dim3(NTH), lds, st, g, P_dev, sc, m, s,
+                       (const T*)f_in, (T*)f_out, (T*)w, (T*)comp, dt);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// P (host copy) sets the stencil scales; P_dev (device copy of the same
+// values) is what the kernel's physics reads.
+hipError_t launch_rk3_split(const Grid& g, const Phys& P, const Phys* P_dev, int precision, int s,
+                            const void* f_in, void* f_out, void* w, void* comp, double dt,
+                            hipStream_t st)
+{
+    switch (precision) {
+    case MHD_F64: return launch_one<MHD_F64>(g, P, P_dev, s, f_in, f_out, w, nullptr, dt, st);
+    case MHD_F32C: return launch_one<MHD_F32C>(g, P, P_dev, s, f_in, f_out, w, comp, dt, st);
+    default: return launch_one<MHD_F32>(g, P, P_dev, s, f_in, f_out, w, nullptr, dt, st);
+    }
+}
+
+}  // namespace mhd

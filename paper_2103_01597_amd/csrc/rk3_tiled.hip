@@ -5,9 +5,10 @@
 //
 // On-chip data flow (FP64: 136 KB of LDS, one workgroup per CU):
 //   * LDS ring of 4 halo'd planes (t .. t+3) of all 8 fields, each plane the
-//     tile plus a 3-cell halo in x and y (38 x 14 cells).  Plane t+4 is
-//     fetched into registers while plane t is computed and enters the ring
-//     at the next iteration, so the HBM stream overlaps the arithmetic.
+//     tile plus a 3-cell halo in x and y (38 x 14 cells).  Plane t+5 is
+//     fetched into registers while plane t is computed; plane t+4 (fetched
+//     one iteration earlier) replaces plane t in the ring at the end of the
+//     iteration, so the HBM stream overlaps the arithmetic.
 //   * x/y first, second and xy-mixed derivatives of plane t read the
 //     plane-t slot (axis lines and planar diagonals of Eq. stencil-fd).
 //   * z derivatives use the thread's own column: planes t-3..t-1 from a
@@ -22,19 +23,39 @@
 // neighbouring tiles of one round run concurrently on the same XCD (see
 // tile_of_block), so halo fetches mostly hit its L2.
 //
+// Stencil weights are the integers of the sixth-order formulas (exact as
+// f64/f32 literals) with one scale factor per axis or plane:
+//   D_a f  = [45 d1 - 9 d2 + d3] / (60 h_a)
+//   D_aa f = [-490 f0 + 270 s1 - 27 s2 + 2 s3] / (180 h_a^2)
+//   D_ab f = [270 e1 - 27 e2 + 2 e3] / (720 h_a h_b)
 // The right-hand side assembly and the 2N update are the same as in the
 // direct kernel (Appendix B; Williamson RK3).
+#include <type_traits>
+
 #include "mhd_internal.hpp"
 #include "rk3_common.hpp"
 
 namespace mhd {
 namespace {
 
-constexpr int TX = 32, TY = 8, NT = TX * TY;
+#ifndef MHD_TILED_TX
+#define MHD_TILED_TX 32
+#endif
+constexpr int TX = MHD_TILED_TX, TY = 256 / MHD_TILED_TX, NT = TX * TY;
 constexpr int HX = TX + 2 * R, HY = TY + 2 * R, PLANE = HX * HY;  // 38 x 14 = 532
 constexpr int SLOT = NQ * PLANE;
 constexpr int NSLOT = 4;
-constexpr int LOADS = (PLANE + NT - 1) / NT;  // 3 loads per field per thread
+constexpr int FULL = PLANE / NT;     // plane elements every thread loads
+constexpr int EXTRA = PLANE % NT;    // threads that load one more element
+// Scheduling fences between the per-field derivative phases (bit i: after
+// phase i) bound the live ranges of the LDS reads the scheduler may hoist.
+#ifndef MHD_TILED_FENCES
+#define MHD_TILED_FENCES 0xFF
+#endif
+constexpr unsigned FENCE_MASK = MHD_TILED_FENCES;
+#ifndef MHD_TILED_F32_BLOCKS
+#define MHD_TILED_F32_BLOCKS 1
+#endif
 
 template <typename T>
 constexpr size_t lds_bytes() { return sizeof(T) * NSLOT * SLOT; }
@@ -44,13 +65,22 @@ struct TileMap {
     int round;      // workgroups resident at once (0: plain order)
 };
 
+// Per-axis scale factors of the integer-weight stencils.
+struct Scales {
+    double d1[3];   // 1/(60 h_a)
+    double d2[3];   // 1/(180 h_a^2)
+    double mxy;     // 1/(720 h_x h_y)
+    double wxz[3];  // {270, -27, 2}/(720 h_x h_z)
+    double wyz[3];  // {270, -27, 2}/(720 h_y h_z)
+};
+
 constexpr int NO_TILE = -1;
 
 // Workgroup b -> tile.  Hardware hands consecutive workgroups to the 8 XCDs
 // in turn; within one round of `round` resident workgroups, XCD k gets the
-// k-th contiguous run of round/8 tiles in row-major tile order, so the tiles
-// that run together on one XCD (sharing its L2) are spatial neighbours, and
-// a round covers a compact band of tile rows.
+// k-th contiguous run of tiles (row-major tile order), so the tiles that run
+// together on one XCD (sharing its L2) are spatial neighbours, and a round
+// covers a compact band of tile rows.
 __device__ __forceinline__ int tile_of_block(int b, const TileMap& m)
 {
     const int tiles = m.ntx * m.nty;
@@ -64,8 +94,16 @@ __device__ __forceinline__ int tile_of_block(int b, const TileMap& m)
     return t < r * m.round + rem ? t : NO_TILE;
 }
 
+// FP64 needs most of a CU's LDS for one workgroup's ring.  The FP32 rings
+// are half that size, but two resident workgroups would cap a lane at 256
+// registers, and the FP64 second-derivative sums of the FP32 variants then
+// spill (measured at 512^3: 7.0 GCUPS with two workgroups per CU against
+// 13.6 with one), so both are built for one.
 template <int PREC>
-__global__ __launch_bounds__(NT, 1) void k_rk3_tiled(Grid g, Phys P, TileMap map, int s,
+constexpr int blocks_per_cu() { return PREC == MHD_F64 ? 1 : MHD_TILED_F32_BLOCKS; }
+
+template <int PREC>
+__global__ __launch_bounds__(NT, blocks_per_cu<PREC>()) void k_rk3_tiled(Grid g, Phys P, Scales sc, TileMap map, int s,
                                                      const typename Prec<PREC>::T* __restrict__ fin,
                                                      typename Prec<PREC>::T* __restrict__ fout,
                                                      typename Prec<PREC>::T* __restrict__ w,
@@ -84,56 +122,65 @@ __global__ __launch_bounds__(NT, 1) void k_rk3_tiled(Grid g, Phys P, TileMap map
     const int x0 = tx * TX, y0 = ty * TY;
     const int tid = threadIdx.x, lx = tid % TX, ly = tid / TX;
     const bool active = (x0 + lx < g.nx) && (y0 + ly < g.ny);
+    const bool extra = tid < EXTRA;
 
-    // ---- per-thread load slots: element e of the halo'd tile plane
-    unsigned goff[LOADS];
-    int lofs[LOADS];
-    bool lval[LOADS];
+    // Global addressing: a uniform field base plus a 32-bit byte offset (every
+    // padded field is below 4 GiB), so loads and stores use the SGPR-base form.
+    auto field_ptr = [&](auto* base, int q) { return base + q * g.fstride; };
+    auto at = [](auto* p, unsigned idx) {
+        using P = decltype(p);
+        using C = typename std::conditional<std::is_const<typename std::remove_pointer<P>::type>::value,
+                                            const char*, char*>::type;
+        return reinterpret_cast<P>(reinterpret_cast<C>(p) + idx * (unsigned)sizeof(T));
+    };
+
+    // ---- per-thread load slots: elements tid, tid + 256 (and tid + 512 for
+    // the first EXTRA threads) of the halo'd tile plane, clamped into the
+    // padded grid for ragged tiles
+    constexpr int NLOAD = FULL + (EXTRA > 0 ? 1 : 0);
+    unsigned goff[NLOAD];
 #pragma unroll
-    for (int k = 0; k < LOADS; ++k) {
-        const int e = tid + k * NT;
-        lval[k] = e < PLANE;
-        const int r = lval[k] ? e / HX : 0, c = lval[k] ? e - (e / HX) * HX : 0;
+    for (int k = 0; k < NLOAD; ++k) {
+        const int e = min(tid + k * NT, PLANE - 1);
+        const int r = e / HX, c = e - r * HX;
         const int px = min(x0 + c, g.mx - 1), py = min(y0 + r, g.my - 1);
         goff[k] = (unsigned)(py * g.mx + px);
-        lofs[k] = lval[k] ? e : 0;
     }
-    const T* fq[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) fq[q] = fin + q * g.fstride;
 
-    T pre[NQ][LOADS];
+    T pre[NQ][NLOAD];
     auto load_plane = [&](int t) {  // t: interior plane index, -3 .. nz+2
         const unsigned zo = (unsigned)((t + R) * g.mxy);
 #pragma unroll
-        for (int q = 0; q < NQ; ++q)
+        for (int q = 0; q < NQ; ++q) {
+            const T* f = field_ptr(fin, q);
 #pragma unroll
-            for (int k = 0; k < LOADS; ++k)
-                if (lval[k]) pre[q][k] = fq[q][goff[k] + zo];
+            for (int k = 0; k < FULL; ++k) pre[q][k] = *at(f, goff[k] + zo);
+        }
+        if constexpr (EXTRA > 0) {
+            if (extra) {
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) pre[q][FULL] = *at(field_ptr(fin, q), goff[FULL] + zo);
+            }
+        }
     };
     auto store_plane = [&](int slot) {
-        T* base = lds + slot * SLOT;
+        T* base = lds + slot * SLOT + tid;
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
 #pragma unroll
-            for (int k = 0; k < LOADS; ++k)
-                if (lval[k]) base[q * PLANE + lofs[k]] = pre[q][k];
+            for (int k = 0; k < FULL; ++k) base[q * PLANE + k * NT] = pre[q][k];
+        if constexpr (EXTRA > 0) {
+            if (extra) {
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) base[q * PLANE + FULL * NT] = pre[q][FULL];
+            }
+        }
     };
 
     const int cofs = (ly + R) * HX + (lx + R);  // own cell within a plane
     auto V = [&](int slot, int q, int dy, int dx) -> T {
         return lds[slot * SLOT + q * PLANE + cofs + dy * HX + dx];
     };
-
-    // ---- constants
-    const Rt ihx = Rt(P.inv_h[0]), ihy = Rt(P.inv_h[1]), ihz = Rt(P.inv_h[2]);
-    const D2 ihx2 = D2(P.inv_h[0] * P.inv_h[0]), ihy2 = D2(P.inv_h[1] * P.inv_h[1]),
-             ihz2 = D2(P.inv_h[2] * P.inv_h[2]);
-    const D2 ihxy = D2(P.inv_h[0] * P.inv_h[1]);
-    const D2 wxz[3] = {D2(CM_1 * P.inv_h[0] * P.inv_h[2]), D2(CM_2 * P.inv_h[0] * P.inv_h[2]),
-                       D2(CM_3 * P.inv_h[0] * P.inv_h[2])};
-    const D2 wyz[3] = {D2(CM_1 * P.inv_h[1] * P.inv_h[2]), D2(CM_2 * P.inv_h[1] * P.inv_h[2]),
-                       D2(CM_3 * P.inv_h[1] * P.inv_h[2])};
 
     // ---- z state: own-column history (planes t-3, t-2, t-1) and the past
     // halves of the six xz/yz mixed combinations for outputs t+1, t+2, t+3:
@@ -149,243 +196,253 @@ __global__ __launch_bounds__(NT, 1) void k_rk3_tiled(Grid g, Phys P, TileMap map
     for (int c = 0; c < 6; ++c)
 #pragma unroll
         for (int k = 0; k < 3; ++k) past[c][k] = D2(0);
+    T wold[NQ] = {}, wnew[NQ] = {}, fnew[NQ] = {}, cc[NQ] = {};
 
-    const int slot_of_minus = 8;  // keeps (t + slot_of_minus) non-negative
+    auto cell_index = [&](int t) { return g.interior + t * g.mxy + (y0 + ly) * g.mx + (x0 + lx); };
+
+    constexpr int SOFS = 8;  // keeps (t + SOFS) non-negative for slot arithmetic
     load_plane(-3);
-    for (int t = -6; t < g.nz; ++t) {
-        const int N = t + 3;  // plane entering the ring
-        __syncthreads();      // slot of plane N held plane N-4, last read at t-1
-        store_plane((N + slot_of_minus) & 3);
-        __syncthreads();
-        if (N + 1 <= g.nz + 2) load_plane(N + 1);
-        if (t < -3) continue;
+    for (int t = -7; t < g.nz; ++t) {
+        if (t >= -3) {
+            const int s0 = (t + SOFS) & 3, s1 = (t + 1 + SOFS) & 3, s2 = (t + 2 + SOFS) & 3,
+                      s3 = (t + 3 + SOFS) & 3;
+            const int sl[4] = {s0, s1, s2, s3};
+            const bool out = t >= 0;  // uniform: warm-up planes only feed the z state
 
-        const int s0 = (t + slot_of_minus) & 3, s1 = (t + 1 + slot_of_minus) & 3,
-                  s2 = (t + 2 + slot_of_minus) & 3, s3 = (t + 3 + slot_of_minus) & 3;
+            Derivs<Rt> d;
+            D2 gdu[3] = {D2(0), D2(0), D2(0)}, jmu[3] = {D2(0), D2(0), D2(0)};
 
-        const int sl[4] = {s0, s1, s2, s3};
-        const bool out = t >= 0;  // uniform: warm-up planes only feed the z state
-
-        // Derivative accumulators of the output cell (filled field by field).
-        Derivs<Rt> d;
-        D2 gdu[3] = {D2(0), D2(0), D2(0)}, jmu[3] = {D2(0), D2(0), D2(0)};
-        T wold[NQ] = {};
-        const int c = g.interior + t * g.mxy + (y0 + ly) * g.mx + (x0 + lx);
-        if (out && s > 0 && active) {
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) wold[q] = w[q * g.fstride + c];
-        }
-
-        // x (dir 0) or y (dir 1) differences d_m = f(+m) - f(-m) of plane t,
-        // and the matching sums s_m = f(+m) + f(-m)
-        auto diff = [&](int q, int dir, int m) {
-            return dir == 0 ? D2(V(s0, q, 0, m)) - D2(V(s0, q, 0, -m))
-                            : D2(V(s0, q, m, 0)) - D2(V(s0, q, -m, 0));
-        };
-        auto sum2 = [&](int q, int dir, int m) {
-            return dir == 0 ? D2(V(s0, q, 0, m)) + D2(V(s0, q, 0, -m))
-                            : D2(V(s0, q, m, 0)) + D2(V(s0, q, -m, 0));
-        };
-        auto first = [&](int q, int dir) -> Rt {  // D_x / D_y in the first-derivative type
-            auto g1 = [&](int m) -> Rt {
-                return dir == 0 ? Rt(V(s0, q, 0, m)) - Rt(V(s0, q, 0, -m))
-                                : Rt(V(s0, q, m, 0)) - Rt(V(s0, q, -m, 0));
+            auto sum2 = [&](int q, int dir, int m) {
+                return dir == 0 ? D2(V(s0, q, 0, m)) + D2(V(s0, q, 0, -m))
+                                : D2(V(s0, q, m, 0)) + D2(V(s0, q, -m, 0));
             };
-            return (Rt(C1_1) * g1(1) + Rt(C1_2) * g1(2) + Rt(C1_3) * g1(3)) * (dir == 0 ? ihx : ihy);
-        };
-        auto col = [&](int q, int k) -> T {  // own column, plane t+k, k = -3..3
-            return k < 0 ? hist[k + 3][q] : V(sl[k], q, 0, 0);
-        };
-        auto dz1 = [&](int q) -> Rt {
-            return (Rt(C1_1) * (Rt(col(q, 1)) - Rt(col(q, -1))) +
-                    Rt(C1_2) * (Rt(col(q, 2)) - Rt(col(q, -2))) +
-                    Rt(C1_3) * (Rt(col(q, 3)) - Rt(col(q, -3)))) * ihz;
-        };
-        // second derivative D_aa along x, y, z (returned individually)
-        auto second = [&](int q, D2& xx, D2& yy, D2& zz) {
-            const D2 f0 = D2(C2_0) * D2(V(s0, q, 0, 0));
-            xx = (D2(C2_1) * sum2(q, 0, 1) + D2(C2_2) * sum2(q, 0, 2) + D2(C2_3) * sum2(q, 0, 3) + f0) * ihx2;
-            yy = (D2(C2_1) * sum2(q, 1, 1) + D2(C2_2) * sum2(q, 1, 2) + D2(C2_3) * sum2(q, 1, 3) + f0) * ihy2;
-            zz = (D2(C2_1) * (D2(col(q, 1)) + D2(col(q, -1))) +
-                  D2(C2_2) * (D2(col(q, 2)) + D2(col(q, -2))) +
-                  D2(C2_3) * (D2(col(q, 3)) + D2(col(q, -3))) + f0) * ihz2;
-        };
-        auto dxy = [&](int q) -> D2 {
-            const D2 cm[3] = {D2(CM_1), D2(CM_2), D2(CM_3)};
-            D2 acc = D2(0);
-#pragma unroll
-            for (int m = 1; m <= 3; ++m)
-                acc += cm[m - 1] * ((D2(V(s0, q, m, m)) + D2(V(s0, q, -m, -m))) -
-                                    (D2(V(s0, q, -m, m)) + D2(V(s0, q, m, -m))));
-            return acc * ihxy;
-        };
-        // xz (dir 0) / yz (dir 1) mixed derivative of field q for combination
-        // cb: the future half from ring planes t+1..t+3 minus the carried past
-        // half (when `first_of_combo`), then the combination's carried state
-        // is advanced by plane t's own differences.
-        auto mixed = [&](int q, int dir, int cb, bool first_of_combo) -> D2 {
-            const D2* wm = dir == 0 ? wxz : wyz;
-            D2 res = D2(0);
-            if (out) {
-#pragma unroll
-                for (int m = 1; m <= 3; ++m) {
-                    const int sm = sl[m];
-                    const D2 dd = dir == 0 ? D2(V(sm, q, 0, m)) - D2(V(sm, q, 0, -m))
-                                           : D2(V(sm, q, m, 0)) - D2(V(sm, q, -m, 0));
-                    res += wm[m - 1] * dd;
+            auto first = [&](int q, int dir) -> Rt {  // D_x / D_y
+                auto g1 = [&](int m) -> Rt {
+                    return dir == 0 ? Rt(V(s0, q, 0, m)) - Rt(V(s0, q, 0, -m))
+                                    : Rt(V(s0, q, m, 0)) - Rt(V(s0, q, -m, 0));
+                };
+                return (Rt(45) * g1(1) - Rt(9) * g1(2) + g1(3)) * Rt(sc.d1[dir]);
+            };
+            auto col = [&](int q, int k) -> T {  // own column, plane t+k, k = -3..3
+                return k < 0 ? hist[k + 3][q] : V(sl[k], q, 0, 0);
+            };
+            auto dz1 = [&](int q) -> Rt {
+                return (Rt(45) * (Rt(col(q, 1)) - Rt(col(q, -1))) -
+                        Rt(9) * (Rt(col(q, 2)) - Rt(col(q, -2))) +
+                        (Rt(col(q, 3)) - Rt(col(q, -3)))) * Rt(sc.d1[2]);
+            };
+            // pure second derivatives along x, y, z
+            auto second = [&](int q, D2& xx, D2& yy, D2& zz) {
+                const D2 f0 = D2(-490) * D2(V(s0, q, 0, 0));
+                xx = (D2(270) * sum2(q, 0, 1) - D2(27) * sum2(q, 0, 2) + D2(2) * sum2(q, 0, 3) + f0) *
+                     D2(sc.d2[0]);
+                yy = (D2(270) * sum2(q, 1, 1) - D2(27) * sum2(q, 1, 2) + D2(2) * sum2(q, 1, 3) + f0) *
+                     D2(sc.d2[1]);
+                zz = (D2(270) * (D2(col(q, 1)) + D2(col(q, -1))) -
+                      D2(27) * (D2(col(q, 2)) + D2(col(q, -2))) +
+                      D2(2) * (D2(col(q, 3)) + D2(col(q, -3))) + f0) * D2(sc.d2[2]);
+            };
+            auto dxy = [&](int q) -> D2 {
+                auto e = [&](int m) {
+                    return (D2(V(s0, q, m, m)) + D2(V(s0, q, -m, -m))) -
+                           (D2(V(s0, q, -m, m)) + D2(V(s0, q, m, -m)));
+                };
+                return (D2(270) * e(1) - D2(27) * e(2) + D2(2) * e(3)) * D2(sc.mxy);
+            };
+            // xz (dir 0) / yz (dir 1) mixed derivative of field q for combination
+            // cb: the future half from ring planes t+1..t+3 minus the carried past
+            // half (when `first_of_combo`); then the combination's carried state
+            // is advanced by plane t's own differences.
+            auto mixed = [&](int q, int dir, int cb, bool first_of_combo) -> D2 {
+                const double* wm = dir == 0 ? sc.wxz : sc.wyz;
+                auto dd = [&](int slot, int m) {
+                    return dir == 0 ? D2(V(slot, q, 0, m)) - D2(V(slot, q, 0, -m))
+                                    : D2(V(slot, q, m, 0)) - D2(V(slot, q, -m, 0));
+                };
+                D2 res = D2(0);
+                if (out) {
+                    res = D2(wm[0]) * dd(s1, 1) + D2(wm[1]) * dd(s2, 2) + D2(wm[2]) * dd(s3, 3);
+                    if (first_of_combo) res -= past[cb][0];
                 }
-                if (first_of_combo) res -= past[cb][0];
-            }
-            const D2 c1 = wm[0] * diff(q, dir, 1), c2 = wm[1] * diff(q, dir, 2),
-                     c3 = wm[2] * diff(q, dir, 3);
-            if (first_of_combo) {
-                past[cb][0] = past[cb][1] + c1;
-                past[cb][1] = past[cb][2] + c2;
-                past[cb][2] = c3;
-            } else {
-                past[cb][0] += c1;
-                past[cb][1] += c2;
-                past[cb][2] += c3;
-            }
-            return res;
-        };
-#define MHD_PHASE_FENCE() __builtin_amdgcn_sched_barrier(0)
+                const D2 c1 = D2(wm[0]) * dd(s0, 1), c2 = D2(wm[1]) * dd(s0, 2),
+                         c3 = D2(wm[2]) * dd(s0, 3);
+                if (first_of_combo) {
+                    past[cb][0] = past[cb][1] + c1;
+                    past[cb][1] = past[cb][2] + c2;
+                    past[cb][2] = c3;
+                } else {
+                    past[cb][0] += c1;
+                    past[cb][1] += c2;
+                    past[cb][2] += c3;
+                }
+                return res;
+            };
+#define MHD_PHASE_FENCE(i) \
+    if constexpr (((FENCE_MASK >> (i)) & 1) != 0) __builtin_amdgcn_sched_barrier(0)
 
-        // ---- lnrho
-        if (out) {
-            d.lnrho = Rt(V(s0, 0, 0, 0));
-            d.gl[0] = first(0, 0); d.gl[1] = first(0, 1); d.gl[2] = dz1(0);
-            D2 xx, yy, zz;
-            second(0, xx, yy, zz);
-            d.lapl = Rt(xx + yy + zz);
-        }
-        MHD_PHASE_FENCE();
-        // ---- ss
-        if (out) {
-            d.ss = Rt(V(s0, 4, 0, 0));
-            d.gs[0] = first(4, 0); d.gs[1] = first(4, 1); d.gs[2] = dz1(4);
-            D2 xx, yy, zz;
-            second(4, xx, yy, zz);
-            d.laps = Rt(xx + yy + zz);
-        }
-        MHD_PHASE_FENCE();
-        // ---- ux: grad, lap; D_xx ux -> gdu_x, D_xy ux -> gdu_y, D_xz ux -> gdu_z
-        {
-            const D2 mz = mixed(1, 0, 2, true);
+            // ---- lnrho
             if (out) {
-                d.ux = Rt(V(s0, 1, 0, 0));
-                d.gu[0][0] = first(1, 0); d.gu[0][1] = first(1, 1); d.gu[0][2] = dz1(1);
+                d.lnrho = Rt(V(s0, 0, 0, 0));
+                d.gl[0] = first(0, 0); d.gl[1] = first(0, 1); d.gl[2] = dz1(0);
                 D2 xx, yy, zz;
-                second(1, xx, yy, zz);
-                d.lapu[0] = Rt(xx + yy + zz);
-                gdu[0] += xx;
-                gdu[1] += dxy(1);
-                gdu[2] += mz;
+                second(0, xx, yy, zz);
+                d.lapl = Rt(xx + yy + zz);
             }
-        }
-        MHD_PHASE_FENCE();
-        // ---- uy
-        {
-            const D2 mz = mixed(2, 1, 2, false);
+            MHD_PHASE_FENCE(0);
+            // ---- ss
             if (out) {
-                d.uy = Rt(V(s0, 2, 0, 0));
-                d.gu[1][0] = first(2, 0); d.gu[1][1] = first(2, 1); d.gu[1][2] = dz1(2);
+                d.ss = Rt(V(s0, 4, 0, 0));
+                d.gs[0] = first(4, 0); d.gs[1] = first(4, 1); d.gs[2] = dz1(4);
                 D2 xx, yy, zz;
-                second(2, xx, yy, zz);
-                d.lapu[1] = Rt(xx + yy + zz);
-                gdu[1] += yy;
-                gdu[0] += dxy(2);
-                gdu[2] += mz;
+                second(4, xx, yy, zz);
+                d.laps = Rt(xx + yy + zz);
             }
-        }
-        MHD_PHASE_FENCE();
-        // ---- uz
-        {
-            const D2 mx = mixed(3, 0, 0, true);
-            const D2 my = mixed(3, 1, 1, true);
-            if (out) {
-                d.uz = Rt(V(s0, 3, 0, 0));
-                d.gu[2][0] = first(3, 0); d.gu[2][1] = first(3, 1); d.gu[2][2] = dz1(3);
-                D2 xx, yy, zz;
-                second(3, xx, yy, zz);
-                d.lapu[2] = Rt(xx + yy + zz);
-                gdu[2] += zz;
-                gdu[0] += mx;
-                gdu[1] += my;
+            MHD_PHASE_FENCE(1);
+            // ---- ux: grad, lap; D_xx ux -> gdu_x, D_xy ux -> gdu_y, D_xz ux -> gdu_z
+            {
+                const D2 mz = mixed(1, 0, 2, true);
+                if (out) {
+                    d.ux = Rt(V(s0, 1, 0, 0));
+                    d.gu[0][0] = first(1, 0); d.gu[0][1] = first(1, 1); d.gu[0][2] = dz1(1);
+                    D2 xx, yy, zz;
+                    second(1, xx, yy, zz);
+                    d.lapu[0] = Rt(xx + yy + zz);
+                    gdu[0] += xx;
+                    gdu[1] += dxy(1);
+                    gdu[2] += mz;
+                }
             }
-        }
-        MHD_PHASE_FENCE();
-        // ---- Ax: mu0 j_x gets -(D_yy + D_zz) Ax, j_y gets D_xy Ax, j_z gets D_xz Ax
-        {
-            const D2 mz = mixed(5, 0, 5, true);
-            if (out) {
-                d.dAx_dy = first(5, 1);
-                d.dAx_dz = dz1(5);
-                D2 xx, yy, zz;
-                second(5, xx, yy, zz);
-                d.lapA[0] = Rt(xx + yy + zz);
-                jmu[0] -= yy + zz;
-                jmu[1] += dxy(5);
-                jmu[2] += mz;
+            MHD_PHASE_FENCE(2);
+            // ---- uy
+            {
+                const D2 mz = mixed(2, 1, 2, false);
+                if (out) {
+                    d.uy = Rt(V(s0, 2, 0, 0));
+                    d.gu[1][0] = first(2, 0); d.gu[1][1] = first(2, 1); d.gu[1][2] = dz1(2);
+                    D2 xx, yy, zz;
+                    second(2, xx, yy, zz);
+                    d.lapu[1] = Rt(xx + yy + zz);
+                    gdu[1] += yy;
+                    gdu[0] += dxy(2);
+                    gdu[2] += mz;
+                }
             }
-        }
-        MHD_PHASE_FENCE();
-        // ---- Ay
-        {
-            const D2 mz = mixed(6, 1, 5, false);
-            if (out) {
-                d.dAy_dx = first(6, 0);
-                d.dAy_dz = dz1(6);
-                D2 xx, yy, zz;
-                second(6, xx, yy, zz);
-                d.lapA[1] = Rt(xx + yy + zz);
-                jmu[1] -= xx + zz;
-                jmu[0] += dxy(6);
-                jmu[2] += mz;
+            MHD_PHASE_FENCE(3);
+            // ---- uz
+            {
+                const D2 mx = mixed(3, 0, 0, true);
+                const D2 my = mixed(3, 1, 1, true);
+                if (out) {
+                    d.uz = Rt(V(s0, 3, 0, 0));
+                    d.gu[2][0] = first(3, 0); d.gu[2][1] = first(3, 1); d.gu[2][2] = dz1(3);
+                    D2 xx, yy, zz;
+                    second(3, xx, yy, zz);
+                    d.lapu[2] = Rt(xx + yy + zz);
+                    gdu[2] += zz;
+                    gdu[0] += mx;
+                    gdu[1] += my;
+                }
             }
-        }
-        MHD_PHASE_FENCE();
-        // ---- Az
-        {
-            const D2 mx = mixed(7, 0, 3, true);
-            const D2 my = mixed(7, 1, 4, true);
-            if (out) {
-                d.dAz_dx = first(7, 0);
-                d.dAz_dy = first(7, 1);
-                D2 xx, yy, zz;
-                second(7, xx, yy, zz);
-                d.lapA[2] = Rt(xx + yy + zz);
-                jmu[2] -= xx + yy;
-                jmu[0] += mx;
-                jmu[1] += my;
+            MHD_PHASE_FENCE(4);
+            // ---- Ax: mu0 j_x gets -(D_yy + D_zz) Ax, j_y gets D_xy Ax, j_z gets D_xz Ax
+            {
+                const D2 mz = mixed(5, 0, 5, true);
+                if (out) {
+                    d.dAx_dy = first(5, 1);
+                    d.dAx_dz = dz1(5);
+                    D2 xx, yy, zz;
+                    second(5, xx, yy, zz);
+                    d.lapA[0] = Rt(xx + yy + zz);
+                    jmu[0] -= yy + zz;
+                    jmu[1] += dxy(5);
+                    jmu[2] += mz;
+                }
             }
-        }
-        MHD_PHASE_FENCE();
+            MHD_PHASE_FENCE(5);
+            // ---- Ay
+            {
+                const D2 mz = mixed(6, 1, 5, false);
+                if (out) {
+                    d.dAy_dx = first(6, 0);
+                    d.dAy_dz = dz1(6);
+                    D2 xx, yy, zz;
+                    second(6, xx, yy, zz);
+                    d.lapA[1] = Rt(xx + yy + zz);
+                    jmu[1] -= xx + zz;
+                    jmu[0] += dxy(6);
+                    jmu[2] += mz;
+                }
+            }
+            MHD_PHASE_FENCE(6);
+            // ---- Az
+            {
+                const D2 mx = mixed(7, 0, 3, true);
+                const D2 my = mixed(7, 1, 4, true);
+                if (out) {
+                    d.dAz_dx = first(7, 0);
+                    d.dAz_dy = first(7, 1);
+                    D2 xx, yy, zz;
+                    second(7, xx, yy, zz);
+                    d.lapA[2] = Rt(xx + yy + zz);
+                    jmu[2] -= xx + yy;
+                    jmu[0] += mx;
+                    jmu[1] += my;
+                }
+            }
+            MHD_PHASE_FENCE(7);
 #undef MHD_PHASE_FENCE
 
-        if (out && active) {
+            if (out) {
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                d.gdu[a] = Rt(gdu[a]);
-                d.jmu[a] = Rt(jmu[a]);
+                for (int a = 0; a < 3; ++a) {
+                    d.gdu[a] = Rt(gdu[a]);
+                    d.jmu[a] = Rt(jmu[a]);
+                }
+                Rt rhs[NQ];
+                rhs_physics<Rt>(d, P, rhs);
+#pragma unroll
+                for (int q = 0; q < NQ; ++q)
+                    rk_values<PREC>(s, V(s0, q, 0, 0), wold[q], rhs[q], dt, wnew[q], fnew[q], cc[q]);
             }
-            Rt rhs[NQ];
-            rhs_physics<Rt>(d, P, rhs);
+
+            // ---- advance the own-column history past plane t
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
-                const int64_t o = q * g.fstride + c;
-                rk_update_v<PREC>(s, V(s0, q, 0, 0), wold[q], rhs[q], dt, w + o, fout + o,
-                                  comp ? comp + o : nullptr);
+                hist[0][q] = hist[1][q];
+                hist[1][q] = hist[2][q];
+                hist[2][q] = V(s0, q, 0, 0);
             }
         }
 
-        // ---- advance the own-column history past plane t
+        // ---- plane t+4 replaces plane t in the ring; then this plane's results
+        // go out, then plane t+5 and the next plane's register values are
+        // fetched.  This order keeps every wait on the vector-memory counter
+        // (which covers loads and stores alike, in issue order) behind
+        // operations issued a whole iteration earlier.
+        __syncthreads();  // every read of plane t is done
+        store_plane((t + 4 + SOFS) & 3);
+        if (t >= 0 && active) {
+            const unsigned c = (unsigned)cell_index(t);
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            hist[0][q] = hist[1][q];
-            hist[1][q] = hist[2][q];
-            hist[2][q] = V(s0, q, 0, 0);
+            for (int q = 0; q < NQ; ++q) {
+                *at(field_ptr(w, q), c) = wnew[q];
+                *at(field_ptr(fout, q), c) = fnew[q];
+                if constexpr (PREC == MHD_F32C) *at(field_ptr(comp, q), c) = cc[q];
+            }
         }
+        if (t + 5 <= g.nz + 2) load_plane(t + 5);
+        if (active && t + 1 >= 0 && t + 1 < g.nz) {
+            const unsigned c = (unsigned)cell_index(t + 1);
+            if (s > 0) {
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) wold[q] = *at(field_ptr(w, q), c);
+            }
+            if constexpr (PREC == MHD_F32C) {
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) cc[q] = *at(field_ptr(comp, q), c);
+            }
+        }
+        __syncthreads();  // plane t+4 visible to every wave
     }
 }
 
@@ -413,11 +470,22 @@ hipError_t launch_one(const Grid& g, const Phys& P, int s, const void* f_in, voi
     m.ntx = (g.nx + TX - 1) / TX;
     m.nty = (g.ny + TY - 1) / TY;
     m.round = round;
+    Scales sc;
+    for (int a = 0; a < 3; ++a) {
+        sc.d1[a] = P.inv_h[a] / 60.0;
+        sc.d2[a] = P.inv_h[a] * P.inv_h[a] / 180.0;
+    }
+    sc.mxy = P.inv_h[0] * P.inv_h[1] / 720.0;
+    const double wm[3] = {270.0, -27.0, 2.0};
+    for (int m3 = 0; m3 < 3; ++m3) {
+        sc.wxz[m3] = wm[m3] * P.inv_h[0] * P.inv_h[2] / 720.0;
+        sc.wyz[m3] = wm[m3] * P.inv_h[1] * P.inv_h[2] / 720.0;
+    }
     const int tiles = m.ntx * m.nty;
     // with the XCD mapping the last round may name tiles past the end; those
     // workgroups exit at once
     const int blocks = (round > 0 && (round & 7) == 0) ? (tiles + round - 1) / round * round : tiles;
-    hipLaunchKernelGGL(k_rk3_tiled<PREC>, dim3(blocks), dim3(NT), lds, st, g, P, m, s,
+    hipLaunchKernelGGL(k_rk3_tiled<PREC>, dim3(blocks), dim3(NT), lds, st, g, P, sc, m, s,
                        (const T*)f_in, (T*)f_out, (T*)w, (T*)comp, dt);
     return hipGetLastError();
 }

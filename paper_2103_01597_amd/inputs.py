@@ -38,19 +38,22 @@ def _draw_modes(rng: np.random.Generator, kmax: int, nmodes: int):
     return np.array(ks), phases
 
 
-def fourier_modes(shape, kmax: int, amp, seed, nmodes: int = 4,
-                  lengths=(2 * math.pi,) * 3, dtype=np.float64) -> np.ndarray:
-    """Sum-of-Fourier-modes state. ``shape`` = (nx, ny, nz); ``amp`` is a
-    scalar or 8 per-field amplitudes (a zero amplitude still draws its modes
-    so the other fields do not depend on it)."""
+def fourier_mode_fields(shape, kmax: int, amp, seed, nmodes: int = 4,
+                        lengths=(2 * math.pi,) * 3, out=None):
+    """The fields of ``fourier_modes`` one at a time: yields (q, field) for
+    q = 0..7, each field an (nz, ny, nx) float64 array.  By default all
+    fields are written into one reused buffer, so that a large state costs
+    one field's worth of host memory; ``out`` may name that buffer, or be an
+    (8, nz, ny, nx) array that receives field q in out[q]."""
     nx, ny, nz = shape
     amps = np.broadcast_to(np.asarray(amp, dtype=np.float64), (NQ,))
     rng = np.random.default_rng(seed)
     x = np.arange(nx) * (lengths[0] / nx)
     y = np.arange(ny) * (lengths[1] / ny)
     z = np.arange(nz) * (lengths[2] / nz)
-    out = np.empty((NQ, nz, ny, nx), dtype=np.float64)
+    single = np.empty((nz, ny, nx), dtype=np.float64) if out is None else out
     for q in range(NQ):
+        buf = single[q] if single.ndim == 4 else single
         ks, phases = _draw_modes(rng, kmax, nmodes)
         # cos(a_x x + a_y y + a_z z + phi) = cos(a_z z + phi) C(x, y) - sin(a_z z + phi) S(x, y)
         # with C, S the cosine/sine of a_x x + a_y y: one (nz, 2m) x (2m, ny*nx) product.
@@ -66,7 +69,19 @@ def fourier_modes(shape, kmax: int, amp, seed, nmodes: int = 4,
             xyfac[2 * m + 1] = (sy[:, None] * cx[None, :] + cy[:, None] * sx[None, :]).ravel()
             zfac[:, 2 * m] = amps[q] * np.cos(az * z + ph)
             zfac[:, 2 * m + 1] = -amps[q] * np.sin(az * z + ph)
-        np.matmul(zfac, xyfac, out=out[q].reshape(nz, ny * nx))
+        np.matmul(zfac, xyfac, out=buf.reshape(nz, ny * nx))
+        yield q, buf
+
+
+def fourier_modes(shape, kmax: int, amp, seed, nmodes: int = 4,
+                  lengths=(2 * math.pi,) * 3, dtype=np.float64) -> np.ndarray:
+    """Sum-of-Fourier-modes state. ``shape`` = (nx, ny, nz); ``amp`` is a
+    scalar or 8 per-field amplitudes (a zero amplitude still draws its modes
+    so the other fields do not depend on it)."""
+    nx, ny, nz = shape
+    out = np.empty((NQ, nz, ny, nx), dtype=np.float64)
+    for _ in fourier_mode_fields(shape, kmax, amp, seed, nmodes, lengths, out=out):
+        pass
     return out.astype(dtype, copy=False)
 
 
@@ -95,3 +110,10 @@ def workload_state(name: str, dtype=np.float64, shape=None) -> np.ndarray:
     w = WORKLOADS[name]
     return fourier_modes(shape or w["shape"], w["kmax"], w["amp"], w["seed"],
                          lengths=w.get("lengths", (2 * math.pi,) * 3), dtype=dtype)
+
+
+def workload_fields(name: str, shape=None):
+    """``workload_state`` one field at a time (see ``fourier_mode_fields``)."""
+    w = WORKLOADS[name]
+    return fourier_mode_fields(shape or w["shape"], w["kmax"], w["amp"], w["seed"],
+                               lengths=w.get("lengths", (2 * math.pi,) * 3))

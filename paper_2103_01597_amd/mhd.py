@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libmhd.so")
 
 F64, F32C, F32 = 0, 1, 2
 PRECISIONS = {"f64": F64, "f32c": F32C, "f32": F32}
-KERNELS = {"tiled": 0, "direct": 1}
+KERNELS = {"tiled": 0, "direct": 1, "split": 2}
 RED_OPS = {"sum": 0, "sumsq": 1, "maxabs": 2, "min": 3, "max": 4, "sumexp": 5, "nonfinite": 6}
 FIELD_NAMES = ("lnrho", "ux", "uy", "uz", "ss", "ax", "ay", "az")
 STATUS = {0: "MHD_OK", 1: "MHD_ERR_INVALID", 2: "MHD_ERR_NO_DEVICE", 3: "MHD_ERR_DEVICE",
@@ -161,6 +161,18 @@ class Solver:
         buf = self.empty() if buf is None else buf
         host = torch.from_numpy(np.ascontiguousarray(fields)).to(self.torch_dtype)
         self.interior_view(buf).copy_(host)
+        if fill_halo:
+            self.halo_periodic(buf)
+        return buf
+
+    def upload_fields(self, fields, buf=None, fill_halo=True):
+        """Like ``upload`` from an iterable of (q, (nz, ny, nx) host array),
+        one field at a time (e.g. ``inputs.fourier_mode_fields``)."""
+        import torch
+        buf = self.empty() if buf is None else buf
+        view = self.interior_view(buf)
+        for q, f in fields:
+            view[q].copy_(torch.from_numpy(np.ascontiguousarray(f)).cuda().to(self.torch_dtype))
         if fill_halo:
             self.halo_periodic(buf)
         return buf

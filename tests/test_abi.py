@@ -15,7 +15,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared(header):
     text = open(os.path.join(ROOT, "include", header)).read()
-    return sorted(set(re.findall(r"^\s*(?:void|int|const char)\s*\*?\s*(mhd\w*)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:void|int|int64_t|const char)\s*\*?\s*(mhd\w*)\s*\(",
+                                 text, re.M)))
 
 
 @pytest.fixture(scope="module")
@@ -26,8 +27,10 @@ def L():
 
 
 def test_every_declared_symbol_is_exported(L):
-    declared = _declared("mhd.h")
-    assert set(declared) == set(mhd.EXPORTS)
+    from paper_2103_01597_amd import nn
+    declared = _declared("mhd.h") + _declared("mhdnn.h")
+    assert set(_declared("mhd.h")) == set(mhd.EXPORTS)
+    assert set(_declared("mhdnn.h")) == set(nn.EXPORTS)
     out = subprocess.run(["nm", "-D", "--defined-only", mhd.LIB_PATH], capture_output=True,
                          text=True, check=True).stdout
     exported = set(re.findall(r"\bT (\w+)$", out, re.M))
@@ -64,7 +67,7 @@ def _init(L, **kw):
 @pytest.mark.parametrize("bad", [dict(nx=0), dict(ny=-3), dict(precision=3), dict(precision=-1),
                                  dict(gamma=1.0), dict(cp=0.0), dict(mu0=0.0),
                                  dict(lx=float("nan")), dict(lz=-1.0), dict(nu=float("inf")),
-                                 dict(nx=3000, ny=3000, nz=3000), dict(kernel=2),
+                                 dict(nx=3000, ny=3000, nz=3000), dict(kernel=3),
                                  dict(reserved_=1)])
 def test_init_rejects_invalid_config(L, bad):
     rc, ctx = _init(L, **bad)

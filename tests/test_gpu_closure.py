@@ -1,0 +1,342 @@
+"""GPU parity of the closure kernels (through the C ABI) against the FP64
+closure oracle evaluated on the same BF16-rounded inputs and weights.
+
+Bars: FP32 outputs (output-layer forward, weight/bias gradients, Adam)
+normwise relative <= 1e-4 (FP32 accumulation of up to 27*32 products per
+output, or of up to a few thousand cells for weight gradients); BF16
+outputs within 2 BF16 ulps elementwise of the correctly rounded oracle
+value (plus 1e-6 absolute), and normwise <= 5e-3.  Elementwise kernels with
+no reduction (pack, apply, MSE gradient) are bit-exact against a host
+emulation of the same FP32 operations.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import closure as C
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def nn():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_2103_01597_amd import nn as m
+    m.lib()
+    return m
+
+
+def bf16_round(a):
+    """Round to the nearest BF16 (ties to even), returned as float64."""
+    f = np.ascontiguousarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def to_cf(t, batch, n, c):
+    """GPU channels-last [b*cells*c] -> numpy (b, c, z, y, x) float64."""
+    return t.float().cpu().numpy().astype(np.float64).reshape(batch, n, n, n, c).transpose(0, 4, 1, 2, 3)
+
+
+def from_cf(a):
+    """numpy (b, c, z, y, x) -> channels-last flat float32 torch tensor on the GPU."""
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a.transpose(0, 2, 3, 4, 1)).reshape(-1)).float().cuda()
+
+
+def normrel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def bf16_close(got, ref, ulps=2):
+    ulp = np.maximum(np.abs(ref), 1e-30) * 2.0 ** -7
+    return np.all(np.abs(got - ref) <= ulps * ulp + 1e-6)
+
+
+def _weights(nn, cin, cout, seed):
+    import torch
+    rng = np.random.default_rng(seed)
+    w = torch.from_numpy(rng.standard_normal((cout, 27, cin)) * 0.2).float().cuda()
+    wp = torch.empty(32 * 27 * cin, dtype=torch.bfloat16, device="cuda")
+    wt = torch.empty(32 * 27 * cout, dtype=torch.bfloat16, device="cuda")
+    nn.prepare_weights(w, cin, cout, wp, wt)
+    wr = wp.float().cpu().numpy().astype(np.float64).reshape(32, 27, cin)[:cout]
+    return w, wp, wt, wr
+
+
+def test_prepare_weights_layouts(nn):
+    w, wp, wt, wr = _weights(nn, 8, 32, 1)
+    wh = w.cpu().numpy()
+    assert np.array_equal(wr, bf16_round(wh))
+    wtr = wt.float().cpu().numpy().reshape(32, 27, 32)
+    for c in range(32):
+        for t in range(27):
+            exp = bf16_round(wh[:, 26 - t, c]) if c < 8 else np.zeros(32)
+            assert np.array_equal(wtr[c, t], exp)
+
+
+@pytest.mark.parametrize("cin,cout", [(8, 32), (32, 32), (32, 8)])
+@pytest.mark.parametrize("n", [16, 32])
+def test_conv_forward(nn, cin, cout, n):
+    import torch
+    batch = 2
+    say(f"conv fwd cin={cin} cout={cout} n={n}")
+    rng = np.random.default_rng(10 + cin + cout + n)
+    x = torch.from_numpy(rng.standard_normal(batch * n ** 3 * cin)).float().cuda().to(torch.bfloat16)
+    w, wp, wt, wr = _weights(nn, cin, cout, 2)
+    bias = torch.from_numpy(rng.standard_normal(cout) * 0.1).float().cuda()
+    cells = batch * n ** 3
+    y = torch.empty(cells * cout, device="cuda")
+    nn.conv3d_fwd(x, wp, bias, n, batch, cin, cout, 1, y=y)
+    z = torch.empty(cells * cout, dtype=torch.bfloat16, device="cuda")
+    a = torch.empty_like(z)
+    nn.conv3d_fwd(x, wp, bias, n, batch, cin, cout, 0, z=z, a=a)
+    torch.cuda.synchronize()
+    xh = to_cf(x, batch, n, cin)
+    bh = bias.cpu().numpy().astype(np.float64)
+    for b in range(batch):
+        ref = C.conv3d(xh[b], wr, bh)
+        gy = to_cf(y, batch, n, cout)[b]
+        e = normrel(gy, ref)
+        assert e <= 1e-4, e
+        gz = to_cf(z, batch, n, cout)[b]
+        ga = to_cf(a, batch, n, cout)[b]
+        assert bf16_close(gz, ref)
+        assert bf16_close(ga, C.gelu(ref), ulps=3)
+    say(f"  fp32 normwise rel err {e:.2e}")
+
+
+@pytest.mark.parametrize("cin_dz,cprev", [(8, 32), (32, 32)])
+def test_conv_dgrad(nn, cin_dz, cprev):
+    import torch
+    n, batch = 16, 2
+    rng = np.random.default_rng(20 + cin_dz)
+    cells = batch * n ** 3
+    dz = torch.from_numpy(rng.standard_normal(cells * cin_dz)).float().cuda().to(torch.bfloat16)
+    zp = torch.from_numpy(rng.standard_normal(cells * cprev)).float().cuda().to(torch.bfloat16)
+    # layer weights w[o = cin_dz][27][c = cprev]
+    w, wp, wt, wr = _weights(nn, cprev, cin_dz, 3)
+    out = torch.empty(cells * cprev, dtype=torch.bfloat16, device="cuda")
+    nn.conv3d_dgrad(dz, wt, zp, n, batch, cin_dz, cprev, out)
+    torch.cuda.synchronize()
+    dzh, zph = to_cf(dz, batch, n, cin_dz), to_cf(zp, batch, n, cprev)
+    got = to_cf(out, batch, n, cprev)
+    for b in range(batch):
+        _, _, dx = C.conv3d_backward(np.zeros((cprev, n, n, n)), wr, dzh[b])
+        ref = dx * C.gelu_grad(zph[b])
+        assert normrel(got[b], ref) <= 5e-3
+        assert bf16_close(got[b], ref, ulps=3)
+
+
+@pytest.mark.parametrize("cin,cout", [(8, 32), (32, 32), (32, 8)])
+@pytest.mark.parametrize("n,batch", [(16, 2), (32, 1)])
+def test_conv_wgrad(nn, cin, cout, n, batch):
+    import torch
+    rng = np.random.default_rng(30 + cin + cout + n)
+    cells = batch * n ** 3
+    x = torch.from_numpy(rng.standard_normal(cells * cin)).float().cuda().to(torch.bfloat16)
+    dz = torch.from_numpy(rng.standard_normal(cells * cout)).float().cuda().to(torch.bfloat16)
+    ws = torch.empty(nn.wgrad_workspace_floats(n, batch), device="cuda")
+    dw = torch.empty(cout * 27 * cin, device="cuda")
+    db = torch.empty(cout, device="cuda")
+    nn.conv3d_wgrad(x, dz, n, batch, cin, cout, ws, dw, db)
+    torch.cuda.synchronize()
+    xh, dzh = to_cf(x, batch, n, cin), to_cf(dz, batch, n, cout)
+    refw = np.zeros((cout, 27, cin))
+    refb = np.zeros(cout)
+    for b in range(batch):
+        w0 = np.zeros((cout, 27, cin))
+        gw, gb, _ = C.conv3d_backward(xh[b], w0, dzh[b])
+        refw += gw
+        refb += gb
+    ew = normrel(dw.cpu().numpy().reshape(cout, 27, cin), refw)
+    eb = normrel(db.cpu().numpy(), refb)
+    say(f"wgrad cin={cin} cout={cout} n={n}: dW {ew:.2e} db {eb:.2e}")
+    assert ew <= 1e-4 and eb <= 1e-4
+
+
+def test_wgrad_deterministic(nn):
+    import torch
+    n, batch, cin, cout = 16, 2, 32, 32
+    rng = np.random.default_rng(5)
+    cells = batch * n ** 3
+    x = torch.from_numpy(rng.standard_normal(cells * cin)).float().cuda().to(torch.bfloat16)
+    dz = torch.from_numpy(rng.standard_normal(cells * cout)).float().cuda().to(torch.bfloat16)
+    ws = torch.empty(nn.wgrad_workspace_floats(n, batch), device="cuda")
+    outs = []
+    for _ in range(2):
+        dw = torch.empty(cout * 27 * cin, device="cuda")
+        db = torch.empty(cout, device="cuda")
+        nn.conv3d_wgrad(x, dz, n, batch, cin, cout, ws, dw, db)
+        outs.append((dw.cpu(), db.cpu()))
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+
+
+def test_network_forward_backward(nn):
+    import torch
+    n, batch = 16, 1
+    rng = np.random.default_rng(40)
+    net = nn.Closure(seed=3)
+    cells = batch * n ** 3
+    x = torch.from_numpy(rng.standard_normal(cells * 8)).float().cuda().to(torch.bfloat16)
+    target = torch.from_numpy(rng.standard_normal(cells * 8) * 0.5).float().cuda()
+    y, cache = net.forward(x, n, batch)
+    dy = torch.empty(cells * 8, dtype=torch.bfloat16, device="cuda")
+    part = torch.empty(256, device="cuda")
+    nn.mse(y, target, dy, part)
+    grads = net.backward(cache, dy, n, batch)
+    torch.cuda.synchronize()
+    # oracle with the same BF16 weights and input
+    params = []
+    for (cin, cout, _), wp, b in zip(nn.LAYERS, net.w_pad, net.b):
+        params.append((wp.float().cpu().numpy().astype(np.float64).reshape(32, 27, cin)[:cout],
+                       b.cpu().numpy().astype(np.float64)))
+    xh = to_cf(x, batch, n, 8)[0]
+    th = to_cf(target, batch, n, 8)[0]
+    yr, cr = C.forward(params, xh)
+    lr = C.mse(yr, th)
+    lg = float(part.sum())
+    say(f"loss gpu {lg:.6f} oracle {lr:.6f}")
+    assert abs(lg - lr) <= 1e-2 * lr
+    assert normrel(to_cf(y, batch, n, 8)[0], yr) <= 2e-2
+    gr, _ = C.backward(params, cr, C.mse_grad(yr, th))
+    for i in range(3):
+        ew = normrel(grads[2 * i].cpu().numpy(), gr[i][0])
+        eb = normrel(grads[2 * i + 1].cpu().numpy(), gr[i][1])
+        say(f"  layer {i}: dW {ew:.2e} db {eb:.2e}")
+        assert ew <= 3e-2 and eb <= 3e-2
+
+
+def test_training_reduces_loss(nn):
+    import torch
+    n, batch = 16, 2
+    rng = np.random.default_rng(41)
+    net = nn.Closure(seed=4)
+    cells = batch * n ** 3
+    x = torch.from_numpy(rng.standard_normal(cells * 8)).float().cuda().to(torch.bfloat16)
+    # a learnable target: a fixed smoothing of the input
+    xs = to_cf(x, batch, n, 8)
+    tgt = 0.5 * (np.roll(xs, 1, axis=-1) + np.roll(xs, -1, axis=-2))
+    target = from_cf(tgt)
+    dy = torch.empty(cells * 8, dtype=torch.bfloat16, device="cuda")
+    part = torch.empty(256, device="cuda")
+    losses = []
+    for it in range(40):
+        y, cache = net.forward(x, n, batch)
+        nn.mse(y, target, dy, part)
+        losses.append(float(part.sum()))
+        grads = net.backward(cache, dy, n, batch)
+        net.step(grads, lr=3e-3)
+    say(f"loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    assert losses[-1] < 0.3 * losses[0]
+
+
+def test_adam_matches_oracle(nn):
+    import torch
+    rng = np.random.default_rng(6)
+    p = rng.standard_normal(1000)
+    m = np.zeros(1000)
+    v = np.zeros(1000)
+    pt, mt, vt = (torch.from_numpy(a).float().cuda() for a in (p, m, v))
+    for t in range(1, 6):
+        g = rng.standard_normal(1000)
+        nn.adam(pt, torch.from_numpy(g).float().cuda(), mt, vt, 1e-2, t)
+        p, m, v = C.adam(p, np.float32(g).astype(np.float64), m, v, t, 1e-2)
+    assert normrel(pt.cpu().numpy(), p) <= 1e-6
+
+
+def test_mse_and_pack_and_apply_exact(nn):
+    import torch
+    from paper_2103_01597_amd import mhd
+    rng = np.random.default_rng(7)
+    # MSE gradient
+    y = rng.standard_normal(5000).astype(np.float32)
+    t = rng.standard_normal(5000).astype(np.float32)
+    dy = torch.empty(5000, dtype=torch.bfloat16, device="cuda")
+    part = torch.empty(256, device="cuda")
+    nn.mse(torch.from_numpy(y).cuda(), torch.from_numpy(t).cuda(), dy, part)
+    exp = bf16_round(np.float32(2.0 / 5000) * (y - t))
+    assert np.array_equal(dy.float().cpu().numpy().astype(np.float64), exp)
+    assert abs(float(part.sum()) - math.fsum(((y - t).astype(np.float64) ** 2).tolist()) / 5000) < 1e-5
+    # pack from an unpadded field-major array
+    n = 16
+    f = rng.standard_normal((8, n, n, n)).astype(np.float32)
+    mean = rng.standard_normal(8).astype(np.float32)
+    inv = (rng.random(8) + 0.5).astype(np.float32)
+    out = torch.empty(n ** 3 * 8, dtype=torch.bfloat16, device="cuda")
+    nn.pack(torch.from_numpy(f).cuda(), n, 1, mean, inv, out)
+    exp = bf16_round((f - mean[:, None, None, None]) * inv[:, None, None, None])
+    assert np.array_equal(to_cf(out, 1, n, 8)[0], exp)
+    # pack from a solver buffer equals pack from its interior
+    S = mhd.Solver(n, n, n, "f32c")
+    buf = S.upload(f.astype(np.float64))
+    out2 = torch.empty_like(out)
+    nn.pack_solver(S, buf, mean, inv, out2)
+    assert torch.equal(out, out2)
+    # pack of a difference of two solver buffers (a coarse step's tendency)
+    g = rng.standard_normal((8, n, n, n)).astype(np.float32)
+    buf2 = S.upload(g.astype(np.float64))
+    out3 = torch.empty_like(out)
+    nn.pack_solver(S, buf, mean, inv, out3, sub=buf2)
+    exp = bf16_round(((f - g).astype(np.float32) - mean[:, None, None, None]) * inv[:, None, None, None])
+    assert np.array_equal(to_cf(out3, 1, n, 8)[0], exp)
+    # apply with compensation
+    comp = S.zeros()
+    S.interior_view(comp).copy_(torch.from_numpy(rng.standard_normal((8, n, n, n)) * 1e-9).float())
+    yv = rng.standard_normal(n ** 3 * 8).astype(np.float32)
+    scale = (rng.random(8) * 1e-3).astype(np.float32)
+    f0 = S.interior_view(buf).cpu().numpy().copy()
+    c0 = S.interior_view(comp).cpu().numpy().copy()
+    nn.apply(S, buf, comp, torch.from_numpy(yv).cuda(), scale)
+    torch.cuda.synchronize()
+    add = (yv.reshape(n, n, n, 8).transpose(3, 0, 1, 2) * scale[:, None, None, None]).astype(np.float32)
+    yc = (add - c0).astype(np.float32)
+    tt = (f0 + yc).astype(np.float32)
+    cc = ((tt - f0).astype(np.float32) - yc).astype(np.float32)
+    assert np.array_equal(S.interior_view(buf).cpu().numpy(), tt)
+    assert np.array_equal(S.interior_view(comp).cpu().numpy(), cc)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32c"])
+def test_box_filter(nn, prec):
+    import torch
+    from paper_2103_01597_amd import mhd
+    n = 32
+    rng = np.random.default_rng(8)
+    f = rng.standard_normal((8, n, n, n))
+    S = mhd.Solver(n, n, n, prec)
+    buf = S.upload(f)
+    coarse = torch.empty(8 * (n // 4) ** 3, device="cuda")
+    nn.box_filter4(S, buf, coarse)
+    torch.cuda.synchronize()
+    host = S.download(buf)
+    ref = C.box_filter4(host)
+    got = coarse.cpu().numpy().reshape(8, n // 4, n // 4, n // 4)
+    assert np.allclose(got, ref, rtol=1e-6, atol=1e-7)
+
+
+def test_closure_gains_over_plain_coarse_run(nn):
+    """Small-scale end-to-end check of the learned closure: fine 64^3 runs of
+    the method, 4x box-filtered to 16^3, train, then a held-out run.  Over
+    the held-out run the corrected coarse run must track the filtered truth
+    better than the plain coarse run (the fallback), on average over the 8
+    fields (per-field errors are printed)."""
+    from paper_2103_01597_amd import closure
+    kw = dict(n_fine=64, kmax=3, dt_fine=2e-3)
+    X, D, _ = closure.generate_pairs(runs=4, pairs_per_run=60, seed_base=100, log=say, **kw)
+    trained, hist = closure.train(X, D, 16, epochs=10, batch=4, lr=2e-3, log=say)
+    ep, ec, truth, plain, corr = closure.evaluate(trained, seed=1000, steps=40, **kw)
+    for i in (0, len(ep) - 1):
+        say(f"step {i + 1} rel L2 plain    :", " ".join("%.3e" % e for e in ep[i]))
+        say(f"step {i + 1} rel L2 corrected:", " ".join("%.3e" % e for e in ec[i]))
+    assert hist[-1] < hist[0]
+    assert np.all(np.isfinite(ec))
+    assert np.mean(ec) < np.mean(ep)

@@ -73,10 +73,11 @@ enum mhd_reduce_op {
 /* ---------------------------------------------------------------- types */
 /* Which fused-substep kernel runs (same results up to rounding order). */
 enum mhd_kernel {
-    MHD_KERNEL_TILED = 0,  /* LDS-tiled z-marching kernel (default) */
+    MHD_KERNEL_TILED = 0,  /* LDS-tiled z-marching kernel */
     MHD_KERNEL_DIRECT = 1, /* one thread per cell, stencil read from global memory */
     MHD_KERNEL_SPLIT = 2   /* LDS-tiled z-march, two threads per cell splitting the
-                              fields (velocity side / entropy-induction side) */
+                              fields (velocity side / entropy-induction side); the
+                              default */
 };
 
 typedef struct mhd_config {
@@ -113,7 +114,7 @@ typedef struct mhd_ctx mhd_ctx;
 
 /* Fill *cfg with the defaults for an n = (nx, ny, nz) grid: l = 2*pi per
  * axis, cs0 = 1, gamma = 5/3, cp = 1, lnrho0 = 0, mu0 = 1,
- * nu = eta = 5e-3, zeta = 0, K = 5e-3, bext = 0, kernel = MHD_KERNEL_TILED.
+ * nu = eta = 5e-3, zeta = 0, K = 5e-3, bext = 0, kernel = MHD_KERNEL_SPLIT.
  * Never fails. */
 void mhd_config_default(mhd_config *cfg, int32_t nx, int32_t ny, int32_t nz,
                         int32_t precision);

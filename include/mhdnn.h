@@ -87,12 +87,33 @@ int mhdnn_conv3d_wgrad(const uint16_t *x, const uint16_t *dz, int32_t n, int32_t
 int mhdnn_prepare_weights(const float *w, int32_t cin, int32_t cout, uint16_t *w_pad,
                           uint16_t *wt_pad, void *stream);
 
-/* Mean-squared error of y against target (count FP32 values each):
- * dy_bf16 = bf16(2 (y - target) / count); loss_partials[b] (device, 256
- * floats) receives per-block partial sums of (y - target)^2 / count in a
- * fixed order (sum them for the loss). */
-int mhdnn_mse(const float *y, const float *target, int64_t count, uint16_t *dy_bf16,
-              float *loss_partials, void *stream);
+/* Mean-squared error of one batch: y is the network output, channels-last
+ * [b][cell][q] (batch * n^3 * 8 floats); the target is field-major
+ * [b][q][cell] (the layout of mhdnn_pair's d) times tscale[q] (8 host
+ * floats).  With e = y - target * tscale over all count = 8 batch n^3
+ * elements: dy_bf16[b][cell][q] = bf16(2 e / count) and loss_partials[k]
+ * (device, 256 floats) receives per-block partial sums of e^2 / count in a
+ * fixed order (their sum is the loss).  n in {16, 32, 64}. */
+int mhdnn_mse(const float *y, const float *target, const float *tscale, int32_t n,
+              int32_t batch, uint16_t *dy_bf16, float *loss_partials, void *stream);
+
+/* One training pair from a coarse step.  `stepped` is the coarse solver
+ * state S after one step (the mhd_layout of `coarse_ctx`, FP32 storage)
+ * taken from the filtered state c_now; c_now and c_next (the next filtered
+ * state) are unpadded field-major [8][n^3].  Writes, field-major:
+ * x_out = S - c_now (the step's tendency, the network input) and
+ * d_out = c_next - S (what the coarse step misses, the target). */
+int mhdnn_pair(const void *coarse_ctx, const void *stepped, const float *c_now,
+               const float *c_next, float *x_out, float *d_out, void *stream);
+
+/* Per-field mean and standard deviation (population, FP64, fixed order)
+ * over npairs samples laid out [p][8][n3] (FP32):
+ * mean_std[q] = mean of field q, mean_std[8 + q] = its standard deviation
+ * (two passes).  `workspace` holds mhdnn_field_stats_workspace_doubles()
+ * doubles; both are device memory. */
+int64_t mhdnn_field_stats_workspace_doubles(void);
+int mhdnn_field_stats(const float *x, int64_t npairs, int64_t n3, double *workspace,
+                      double *mean_std, void *stream);
 
 /* Adam (Kingma & Ba, bias-corrected) on n FP32 parameters:
  * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;

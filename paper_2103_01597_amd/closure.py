@@ -80,9 +80,7 @@ def generate_pairs(n_fine=256, runs=10, pairs_per_run=200, seed_base=5000, kmax=
             _to_coarse_solver(Sc, snap[i], cb[0])
             compc.zero_()
             c = Sc.step(cb, 0, wc, compc, ratio * dt_fine, 1)
-            s_i = Sc.interior_view(cb[c]).reshape(8, -1)
-            X[k] = s_i - snap[i].view(8, -1)
-            D[k] = snap[i + 1].view(8, -1) - s_i
+            nn.pair(Sc, cb[c], snap[i], snap[i + 1], X[k], D[k])
             k += 1
         if log:
             log(f"run {r}: {pairs_per_run} pairs")
@@ -103,16 +101,14 @@ def train(X, D, nc, epochs=5, batch=4, lr=2e-3, seed=0, log=None):
     """Fit the closure on (X, D); returns (Trained, per-epoch mean losses)."""
     import torch
     P = X.shape[0]
-    mean = X.mean(dim=(0, 2)).cpu().numpy()
-    std = X.std(dim=(0, 2)).cpu().numpy()
+    cells = nc ** 3
+    mean, std = nn.field_stats(X, P, cells)
     std = np.where(std > 0, std, 1.0)
-    dstd = D.std(dim=(0, 2)).cpu().numpy()
+    _, dstd = nn.field_stats(D, P, cells)
     dstd = np.where(dstd > 0, dstd, 1.0)
     inv_std = 1.0 / std
-    # normalised targets, channels-last, per sample
-    Dn = (D / torch.from_numpy(dstd).float().cuda()[None, :, None]).permute(0, 2, 1).contiguous()
+    inv_dstd = 1.0 / dstd
     net = nn.Closure(seed=seed)
-    cells = nc ** 3
     xb = torch.empty(batch * cells * 8, dtype=torch.bfloat16, device="cuda")
     dy = torch.empty(batch * cells * 8, dtype=torch.bfloat16, device="cuda")
     part = torch.empty(256, device="cuda")
@@ -124,14 +120,14 @@ def train(X, D, nc, epochs=5, batch=4, lr=2e-3, seed=0, log=None):
         tot, cnt = 0.0, 0
         for s in range(0, P - batch + 1, batch):
             idx = order[s:s + batch]
-            xs = X[idx]  # [batch, 8, cells]
+            xs = X[idx]  # [batch, 8, cells] (gathered copies)
+            ds = D[idx]
             nn.pack(xs, nc, batch, mean, inv_std, xb)
             y, cache = net.forward(xb, nc, batch)
-            tgt = Dn[idx].reshape(-1)
-            nn.mse(y, tgt, dy, part)
+            nn.mse(y, ds, inv_dstd, nc, batch, dy, part)
             grads = net.backward(cache, dy, nc, batch, workspace=ws)
             net.step(grads, lr)
-            tot += float(part.sum())
+            tot += float(np.sum(part.cpu().numpy(), dtype=np.float64))
             cnt += 1
         hist.append(tot / max(cnt, 1))
         if log:
@@ -176,7 +172,8 @@ def evaluate(trained, n_fine=256, seed=9000, steps=50, kmax=8,
         c = 0
         errs = []
         xb = torch.empty(nc ** 3 * 8, dtype=torch.bfloat16, device="cuda")
-        prev = Sc.empty()
+        prev, plain_state, plain_comp = Sc.empty(), Sc.empty(), Sc.empty()
+        fallbacks = 0
         for i in range(steps):
             if mode == "corrected":
                 prev.copy_(cb[c])
@@ -184,8 +181,14 @@ def evaluate(trained, n_fine=256, seed=9000, steps=50, kmax=8,
             if mode == "corrected":
                 nn.pack_solver(Sc, cb[c], trained.mean, trained.inv_std, xb, sub=prev)
                 y, _ = trained.net.forward(xb, nc, 1)
-                if bool(torch.isfinite(y).all()):
-                    nn.apply(Sc, cb[c], comp, y, trained.dscale)
+                plain_state.copy_(cb[c])
+                plain_comp.copy_(comp)
+                nn.apply(Sc, cb[c], comp, y, trained.dscale)
+                if sum(Sc.reduce(cb[c], q, "nonfinite") for q in range(8)) > 0:
+                    # the plain method is the fallback
+                    cb[c].copy_(plain_state)
+                    comp.copy_(plain_comp)
+                    fallbacks += 1
             st = Sc.interior_view(cb[c]).reshape(8, -1)
             errs.append(_rel_l2(st, truth[i + 1].view(8, -1)))
         res[mode] = (np.array(errs), Sc.download(cb[c]))

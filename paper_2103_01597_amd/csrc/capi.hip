@@ -193,6 +193,7 @@ void mhd_config_default(mhd_config* cfg, int32_t nx, int32_t ny, int32_t nz, int
     cfg->zeta = 0.0;
     cfg->eta = 5e-3;
     cfg->K = 5e-3;
+    cfg->kernel = MHD_KERNEL_SPLIT;
 }
 
 const char* mhd_strerror(int status)

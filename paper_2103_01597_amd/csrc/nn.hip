@@ -379,16 +379,23 @@ __global__ void k_box4(Grid g, const E* __restrict__ fine, float* __restrict__ c
     coarse[i] = (float)(s / 64.0);
 }
 
+// Loss and output gradient of one batch: y channels-last [b][cell][q],
+// target field-major [b][q][cell] times tscale[q].
 __global__ __launch_bounds__(NTHR) void k_mse(const float* __restrict__ y,
-                                              const float* __restrict__ t, int64_t count,
-                                              uint16_t* __restrict__ dy, float* __restrict__ part)
+                                              const float* __restrict__ t, Vec8 tscale, int logn3,
+                                              int64_t count, uint16_t* __restrict__ dy,
+                                              float* __restrict__ part)
 {
     __shared__ float sh[NTHR];
     const float scale = 2.0f / (float)count, inv = 1.0f / (float)count;
+    const int64_t n3 = (int64_t)1 << logn3;
     float acc = 0.0f;
     for (int64_t i = (int64_t)blockIdx.x * NTHR + threadIdx.x; i < count;
          i += (int64_t)gridDim.x * NTHR) {
-        const float d = y[i] - t[i];
+        const int q = (int)(i & 7);
+        const int64_t bc = i >> 3, b = bc >> logn3, cell = bc & (n3 - 1);
+        // the scaled target is rounded before the difference (no fused multiply-add)
+        const float d = y[i] - __fmul_rn(t[(b * 8 + q) * n3 + cell], tscale.v[q]);
         dy[i] = f2bf(scale * d);
         acc += d * d * inv;
     }
@@ -399,6 +406,65 @@ __global__ __launch_bounds__(NTHR) void k_mse(const float* __restrict__ y,
         __syncthreads();
     }
     if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// Training pair from a coarse step: x = S - C_now (the step's tendency),
+// d = C_next - S (what the step misses); S in the coarse solver's padded
+// layout, C and the outputs unpadded field-major.
+__global__ void k_pair(Grid g, const float* __restrict__ S, const float* __restrict__ cnow,
+                       const float* __restrict__ cnext, float* __restrict__ x,
+                       float* __restrict__ d)
+{
+    const int64_t n3 = (int64_t)g.nx * g.ny * g.nz;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // q * n3 + cell
+    if (i >= 8 * n3) return;
+    const int q = (int)(i / n3);
+    const int64_t cell = i - q * n3;
+    const int xx = (int)(cell % g.nx), yy = (int)((cell / g.nx) % g.ny), zz = (int)(cell / ((int64_t)g.nx * g.ny));
+    const float sv = S[q * g.fstride + g.interior + (int64_t)zz * g.mxy + (int64_t)yy * g.mx + xx];
+    x[i] = sv - cnow[i];
+    d[i] = cnext[i] - sv;
+}
+
+constexpr int STAT_BLOCKS = 256;  // blocks per field in the statistics pass
+
+// Per-field FP64 partial sums over samples [p][8][n3]: of x (mean == NULL)
+// or of (x - mean[q])^2.  Block b of field q covers a fixed interleaved set
+// of elements; partials[q][b].
+__global__ __launch_bounds__(NTHR) void k_stats(const float* __restrict__ x, int64_t npairs,
+                                                int64_t n3, const double* __restrict__ mean,
+                                                double* __restrict__ partials)
+{
+    __shared__ double sh[NTHR];
+    const int q = blockIdx.y;
+    const double m = mean ? mean[q] : 0.0;
+    const int64_t per = npairs * n3;
+    double acc = 0.0;
+    for (int64_t j = (int64_t)blockIdx.x * NTHR + threadIdx.x; j < per;
+         j += (int64_t)STAT_BLOCKS * NTHR) {
+        const int64_t p = j / n3, cell = j - p * n3;
+        const double v = (double)x[(p * 8 + q) * n3 + cell];
+        acc += mean ? (v - m) * (v - m) : v;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int hh = NTHR / 2; hh > 0; hh >>= 1) {
+        if (threadIdx.x < hh) sh[threadIdx.x] += sh[threadIdx.x + hh];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[q * STAT_BLOCKS + blockIdx.x] = sh[0];
+}
+
+// out[q] = (sum of partials[q][*] in order) / count (then sqrt if `root`).
+__global__ void k_stats_final(const double* __restrict__ partials, double count, int root,
+                              double* __restrict__ out)
+{
+    const int q = threadIdx.x;
+    if (q >= 8) return;
+    double s = 0.0;
+    for (int b = 0; b < STAT_BLOCKS; ++b) s += partials[q * STAT_BLOCKS + b];
+    s /= count;
+    out[q] = root ? sqrt(s) : s;
 }
 
 __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
@@ -590,12 +656,49 @@ int mhdnn_prepare_weights(const float* w, int32_t cin, int32_t cout, uint16_t* w
     return status(hipGetLastError());
 }
 
-int mhdnn_mse(const float* y, const float* target, int64_t count, uint16_t* dy_bf16,
-              float* loss_partials, void* stream)
+int mhdnn_mse(const float* y, const float* target, const float* tscale, int32_t n, int32_t batch,
+              uint16_t* dy_bf16, float* loss_partials, void* stream)
 {
-    if (!y || !target || !dy_bf16 || !loss_partials || count < 1) return MHD_ERR_INVALID;
-    hipLaunchKernelGGL(k_mse, dim3(256), dim3(NTHR), 0, (hipStream_t)stream, y, target, count,
-                       dy_bf16, loss_partials);
+    if (!y || !target || !tscale || !dy_bf16 || !loss_partials || batch < 1) return MHD_ERR_INVALID;
+    const int logn = ilog2(n);
+    if (logn < 0) return MHD_ERR_INVALID;
+    Vec8 ts;
+    for (int q = 0; q < 8; ++q) ts.v[q] = tscale[q];
+    const int64_t count = ((int64_t)batch << (3 * logn)) * 8;
+    hipLaunchKernelGGL(k_mse, dim3(256), dim3(NTHR), 0, (hipStream_t)stream, y, target, ts,
+                       3 * logn, count, dy_bf16, loss_partials);
+    return status(hipGetLastError());
+}
+
+int mhdnn_pair(const void* coarse_ctx, const void* stepped, const float* c_now,
+               const float* c_next, float* x_out, float* d_out, void* stream)
+{
+    if (!coarse_ctx || !stepped || !c_now || !c_next || !x_out || !d_out) return MHD_ERR_INVALID;
+    const mhd_ctx* ctx = (const mhd_ctx*)coarse_ctx;
+    if (ctx_precision(ctx) == MHD_F64) return MHD_ERR_INVALID;
+    const Grid g = *ctx_grid(ctx);
+    const int64_t total = 8LL * g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(k_pair, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)stream, g, (const float*)stepped, c_now, c_next, x_out, d_out);
+    return status(hipGetLastError());
+}
+
+int64_t mhdnn_field_stats_workspace_doubles(void) { return 8 * STAT_BLOCKS; }
+
+int mhdnn_field_stats(const float* x, int64_t npairs, int64_t n3, double* workspace,
+                      double* mean_std, void* stream)
+{
+    if (!x || !workspace || !mean_std || npairs < 1 || n3 < 1) return MHD_ERR_INVALID;
+    hipStream_t st = (hipStream_t)stream;
+    const double count = (double)npairs * (double)n3;
+    hipLaunchKernelGGL(k_stats, dim3(STAT_BLOCKS, 8), dim3(NTHR), 0, st, x, npairs, n3,
+                       (const double*)nullptr, workspace);
+    hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(64), 0, st, (const double*)workspace, count,
+                       0, mean_std);
+    hipLaunchKernelGGL(k_stats, dim3(STAT_BLOCKS, 8), dim3(NTHR), 0, st, x, npairs, n3,
+                       (const double*)mean_std, workspace);
+    hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(64), 0, st, (const double*)workspace, count,
+                       1, mean_std + 8);
     return status(hipGetLastError());
 }
 

@@ -102,7 +102,7 @@ class Solver:
     :meth:`grid_view` / :meth:`interior_view` for (8, mz, my, mx) views.
     """
 
-    def __init__(self, nx, ny, nz, precision="f64", kernel="tiled", **phys):
+    def __init__(self, nx, ny, nz, precision="f64", kernel="split", **phys):
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         cfg = Config()
         lib().mhd_config_default(ctypes.byref(cfg), nx, ny, nz, self.precision)

@@ -15,7 +15,9 @@ from . import mhd as _mhd
 
 EXPORTS = ("mhdnn_box_filter4", "mhdnn_pack", "mhdnn_conv3d_fwd", "mhdnn_conv3d_dgrad",
            "mhdnn_wgrad_workspace_floats", "mhdnn_conv3d_wgrad", "mhdnn_prepare_weights",
-           "mhdnn_mse", "mhdnn_adam", "mhdnn_apply")
+           "mhdnn_mse", "mhdnn_pair", "mhdnn_field_stats_workspace_doubles",
+           "mhdnn_field_stats", "mhdnn_adam", "mhdnn_apply")
+_INT64_RESULT = ("mhdnn_wgrad_workspace_floats", "mhdnn_field_stats_workspace_doubles")
 LAYERS = ((8, 32, True), (32, 32, True), (32, 8, False))  # (cin, cout, gelu)
 
 _bound = False
@@ -36,11 +38,15 @@ def lib():
     L.mhdnn_wgrad_workspace_floats.restype = i64
     L.mhdnn_conv3d_wgrad.argtypes = [vp, vp, i32, i32, i32, i32, vp, vp, vp, vp]
     L.mhdnn_prepare_weights.argtypes = [vp, i32, i32, vp, vp, vp]
-    L.mhdnn_mse.argtypes = [vp, vp, i64, vp, vp, vp]
+    L.mhdnn_mse.argtypes = [vp, vp, fp, i32, i32, vp, vp, vp]
+    L.mhdnn_pair.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.mhdnn_field_stats_workspace_doubles.argtypes = []
+    L.mhdnn_field_stats_workspace_doubles.restype = i64
+    L.mhdnn_field_stats.argtypes = [vp, i64, i64, vp, vp, vp]
     L.mhdnn_adam.argtypes = [vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp]
     L.mhdnn_apply.argtypes = [vp, vp, vp, vp, fp, vp]
     for fn in EXPORTS:
-        if fn != "mhdnn_wgrad_workspace_floats":
+        if fn not in _INT64_RESULT:
             getattr(L, fn).restype = ctypes.c_int
     _bound = True
     return L
@@ -108,9 +114,27 @@ def prepare_weights(w, cin, cout, w_pad, wt_pad=None, stream=None):
                                                               _p(wt_pad), _st(stream)))
 
 
-def mse(y, target, dy, partials, stream=None):
-    _chk("mhdnn_mse", lib().mhdnn_mse(_p(y), _p(target), y.numel(), _p(dy), _p(partials),
-                                      _st(stream)))
+def mse(y, target, tscale, n, batch, dy, partials, stream=None):
+    """target: field-major [batch][8][n^3] FP32, scaled per field by tscale."""
+    _chk("mhdnn_mse", lib().mhdnn_mse(_p(y), _p(target), _f8(tscale), n, batch, _p(dy),
+                                      _p(partials), _st(stream)))
+
+
+def pair(coarse_solver, stepped, c_now, c_next, x_out, d_out, stream=None):
+    _chk("mhdnn_pair", lib().mhdnn_pair(coarse_solver._ctx, _p(stepped), _p(c_now), _p(c_next),
+                                        _p(x_out), _p(d_out), _st(stream)))
+
+
+def field_stats(x, npairs, n3, stream=None):
+    """Per-field (mean, std) of samples [npairs][8][n3] as host float64 arrays."""
+    import torch
+    ws = torch.empty(int(lib().mhdnn_field_stats_workspace_doubles()), dtype=torch.float64,
+                     device=x.device)
+    out = torch.empty(16, dtype=torch.float64, device=x.device)
+    _chk("mhdnn_field_stats", lib().mhdnn_field_stats(_p(x), npairs, n3, _p(ws), _p(out),
+                                                      _st(stream)))
+    host = out.cpu().numpy()
+    return host[:8].copy(), host[8:].copy()
 
 
 def adam(p, g, m, v, lr, t, b1=0.9, b2=0.999, eps=1e-8, stream=None):

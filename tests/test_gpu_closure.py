@@ -46,12 +46,6 @@ def to_cf(t, batch, n, c):
     return t.float().cpu().numpy().astype(np.float64).reshape(batch, n, n, n, c).transpose(0, 4, 1, 2, 3)
 
 
-def from_cf(a):
-    """numpy (b, c, z, y, x) -> channels-last flat float32 torch tensor on the GPU."""
-    import torch
-    return torch.from_numpy(np.ascontiguousarray(a.transpose(0, 2, 3, 4, 1)).reshape(-1)).float().cuda()
-
-
 def normrel(a, b):
     return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
 
@@ -187,11 +181,12 @@ def test_network_forward_backward(nn):
     net = nn.Closure(seed=3)
     cells = batch * n ** 3
     x = torch.from_numpy(rng.standard_normal(cells * 8)).float().cuda().to(torch.bfloat16)
-    target = torch.from_numpy(rng.standard_normal(cells * 8) * 0.5).float().cuda()
+    tf = (rng.standard_normal((batch, 8, n ** 3)) * 0.5).astype(np.float32)  # field-major
+    target = torch.from_numpy(tf).cuda()
     y, cache = net.forward(x, n, batch)
     dy = torch.empty(cells * 8, dtype=torch.bfloat16, device="cuda")
     part = torch.empty(256, device="cuda")
-    nn.mse(y, target, dy, part)
+    nn.mse(y, target, np.ones(8), n, batch, dy, part)
     grads = net.backward(cache, dy, n, batch)
     torch.cuda.synchronize()
     # oracle with the same BF16 weights and input
@@ -200,7 +195,7 @@ def test_network_forward_backward(nn):
         params.append((wp.float().cpu().numpy().astype(np.float64).reshape(32, 27, cin)[:cout],
                        b.cpu().numpy().astype(np.float64)))
     xh = to_cf(x, batch, n, 8)[0]
-    th = to_cf(target, batch, n, 8)[0]
+    th = tf[0].astype(np.float64).reshape(8, n, n, n)
     yr, cr = C.forward(params, xh)
     lr = C.mse(yr, th)
     lg = float(part.sum())
@@ -225,13 +220,13 @@ def test_training_reduces_loss(nn):
     # a learnable target: a fixed smoothing of the input
     xs = to_cf(x, batch, n, 8)
     tgt = 0.5 * (np.roll(xs, 1, axis=-1) + np.roll(xs, -1, axis=-2))
-    target = from_cf(tgt)
+    target = torch.from_numpy(tgt.reshape(batch, 8, n ** 3)).float().cuda()  # field-major
     dy = torch.empty(cells * 8, dtype=torch.bfloat16, device="cuda")
     part = torch.empty(256, device="cuda")
     losses = []
     for it in range(40):
         y, cache = net.forward(x, n, batch)
-        nn.mse(y, target, dy, part)
+        nn.mse(y, target, np.ones(8), n, batch, dy, part)
         losses.append(float(part.sum()))
         grads = net.backward(cache, dy, n, batch)
         net.step(grads, lr=3e-3)
@@ -257,17 +252,21 @@ def test_mse_and_pack_and_apply_exact(nn):
     import torch
     from paper_2103_01597_amd import mhd
     rng = np.random.default_rng(7)
-    # MSE gradient
-    y = rng.standard_normal(5000).astype(np.float32)
-    t = rng.standard_normal(5000).astype(np.float32)
-    dy = torch.empty(5000, dtype=torch.bfloat16, device="cuda")
+    # MSE gradient: y channels-last, target field-major with per-field scale
+    n, b = 16, 2
+    y = rng.standard_normal(b * n ** 3 * 8).astype(np.float32)
+    t = rng.standard_normal((b, 8, n ** 3)).astype(np.float32)
+    ts = (rng.random(8) + 0.5).astype(np.float32)
+    cnt = y.size
+    dy = torch.empty(cnt, dtype=torch.bfloat16, device="cuda")
     part = torch.empty(256, device="cuda")
-    nn.mse(torch.from_numpy(y).cuda(), torch.from_numpy(t).cuda(), dy, part)
-    exp = bf16_round(np.float32(2.0 / 5000) * (y - t))
+    nn.mse(torch.from_numpy(y).cuda(), torch.from_numpy(t).cuda(), ts, n, b, dy, part)
+    tl = (t * ts[None, :, None]).astype(np.float32).transpose(0, 2, 1).reshape(-1)
+    e = (y - tl).astype(np.float32)
+    exp = bf16_round(np.float32(2.0 / cnt) * e)
     assert np.array_equal(dy.float().cpu().numpy().astype(np.float64), exp)
-    assert abs(float(part.sum()) - math.fsum(((y - t).astype(np.float64) ** 2).tolist()) / 5000) < 1e-5
+    assert abs(float(part.sum()) - math.fsum((e.astype(np.float64) ** 2).tolist()) / cnt) < 1e-5
     # pack from an unpadded field-major array
-    n = 16
     f = rng.standard_normal((8, n, n, n)).astype(np.float32)
     mean = rng.standard_normal(8).astype(np.float32)
     inv = (rng.random(8) + 0.5).astype(np.float32)
@@ -303,6 +302,35 @@ def test_mse_and_pack_and_apply_exact(nn):
     cc = ((tt - f0).astype(np.float32) - yc).astype(np.float32)
     assert np.array_equal(S.interior_view(buf).cpu().numpy(), tt)
     assert np.array_equal(S.interior_view(comp).cpu().numpy(), cc)
+
+
+def test_pair_and_field_stats(nn):
+    """mhdnn_pair: x = S - C_now, d = C_next - S from a solver buffer (exact
+    FP32 differences); mhdnn_field_stats: per-field mean and population std
+    against float64 numpy."""
+    import torch
+    from paper_2103_01597_amd import mhd
+    rng = np.random.default_rng(11)
+    n = 16
+    S = mhd.Solver(n, n, n, "f32c")
+    sv = rng.standard_normal((8, n, n, n)).astype(np.float32)
+    buf = S.upload(sv.astype(np.float64))
+    cn = rng.standard_normal((8, n ** 3)).astype(np.float32)
+    cx = rng.standard_normal((8, n ** 3)).astype(np.float32)
+    x = torch.empty((8, n ** 3), device="cuda")
+    d = torch.empty_like(x)
+    nn.pair(S, buf, torch.from_numpy(cn).cuda(), torch.from_numpy(cx).cuda(), x, d)
+    flat = sv.reshape(8, -1)
+    assert np.array_equal(x.cpu().numpy(), (flat - cn).astype(np.float32))
+    assert np.array_equal(d.cpu().numpy(), (cx - flat).astype(np.float32))
+    S.close()
+    P, n3 = 5, 3000
+    a = (rng.standard_normal((P, 8, n3)) * rng.random(8)[None, :, None] * 3
+         + rng.standard_normal(8)[None, :, None]).astype(np.float32)
+    mean, std = nn.field_stats(torch.from_numpy(a).cuda(), P, n3)
+    ad = a.astype(np.float64)
+    assert np.allclose(mean, ad.mean(axis=(0, 2)), rtol=1e-12, atol=1e-14)
+    assert np.allclose(std, ad.std(axis=(0, 2)), rtol=1e-12, atol=1e-14)
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32c"])

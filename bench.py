@@ -29,7 +29,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-DEFAULT_KERNEL = "split"
 KERNEL_SOURCE = {"split": "rk3_split.hip", "tiled": "rk3_tiled.hip", "direct": "rk3_direct.hip"}
 KERNEL_SYMBOL = {"split": "k_rk3_split", "tiled": "k_rk3_tiled", "direct": "k_rk3_direct"}
 
@@ -57,6 +56,7 @@ def run_precision(mhd, inputs, torch, name, prec, steps, warmup, kernel):
     n = wl["shape"]
     cells = n[0] * n[1] * n[2]
     S = mhd.Solver(*n, prec, kernel, lengths=wl.get("lengths", (2 * math.pi,) * 3))
+    kernel = S.kernel
     bufs = [S.upload_fields(inputs.workload_fields(name)), S.empty()]
     w = S.zeros()
     comp = S.zeros() if prec == "f32c" else None
@@ -97,6 +97,7 @@ def run_precision(mhd, inputs, torch, name, prec, steps, warmup, kernel):
         kernel_gbs=achieved,
         kernel_gcups=3 * cells * steps / (sum_kern_ms * 1e-3) / 1e9,
         nonfinite=nonfinite,
+        kernel=kernel,
     )
     S.close()
     del bufs, w, comp
@@ -163,8 +164,9 @@ def main():
                          "the large workload)")
     ap.add_argument("--workload", default="prec512",
                     choices=["prec512", "sub256", "large1024x512x512"])
-    ap.add_argument("--kernel", default=DEFAULT_KERNEL, choices=["split", "tiled", "direct"],
-                    help="fused-substep kernel (default: %(default)s)")
+    ap.add_argument("--kernel", default=None, choices=["split", "tiled", "direct"],
+                    help="fused-substep kernel (default: the library's default for each "
+                         "precision: split for f64, tiled otherwise)")
     args = ap.parse_args()
     if args.precisions is None:
         args.precisions = "f32c" if args.workload == "large1024x512x512" else "f64,f32c"
@@ -201,12 +203,12 @@ def main():
         "dtype": main_prec,
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[args.workload], "grid": list(wl["shape"]),
-                   "precision": main_prec, "kernel": args.kernel},
+                   "precision": main_prec, "kernel": r["kernel"]},
         "roofline": {"bound": "hbm", "achieved": round(r["kernel_gbs"], 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(r["kernel_gbs"] / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(args.kernel, main_prec, args.workload),
-                     "kernel": KERNEL_SYMBOL[args.kernel],
+                     "traffic": measured_traffic(r["kernel"], main_prec, args.workload),
+                     "kernel": KERNEL_SYMBOL[r["kernel"]],
                      "kernel_ms_avg": round(r["kernel_ms_avg"], 4)},
     }
     for prec, rr in results.items():
@@ -214,6 +216,8 @@ def main():
             line[f"{prec}_gcups"] = round(rr["gcups"], 4)
             line[f"{prec}_roofline_frac"] = round(rr["kernel_gbs"] / HBM_PEAK_GBS, 4)
             line[f"{prec}_kernel_ms_avg"] = round(rr["kernel_ms_avg"], 4)
+            line[f"{prec}_kernel"] = KERNEL_SYMBOL[rr["kernel"]]
+            line[f"{prec}_traffic"] = measured_traffic(rr["kernel"], prec, args.workload)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(inputs, inputs.WORKLOADS["prec512"])
     print(json.dumps(line), flush=True)

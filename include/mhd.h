@@ -76,8 +76,7 @@ enum mhd_kernel {
     MHD_KERNEL_TILED = 0,  /* LDS-tiled z-marching kernel */
     MHD_KERNEL_DIRECT = 1, /* one thread per cell, stencil read from global memory */
     MHD_KERNEL_SPLIT = 2   /* LDS-tiled z-march, two threads per cell splitting the
-                              fields (velocity side / entropy-induction side); the
-                              default */
+                              fields (velocity side / entropy-induction side) */
 };
 
 typedef struct mhd_config {
@@ -114,7 +113,8 @@ typedef struct mhd_ctx mhd_ctx;
 
 /* Fill *cfg with the defaults for an n = (nx, ny, nz) grid: l = 2*pi per
  * axis, cs0 = 1, gamma = 5/3, cp = 1, lnrho0 = 0, mu0 = 1,
- * nu = eta = 5e-3, zeta = 0, K = 5e-3, bext = 0, kernel = MHD_KERNEL_SPLIT.
+ * nu = eta = 5e-3, zeta = 0, K = 5e-3, bext = 0, kernel = MHD_KERNEL_SPLIT for
+ * MHD_F64 and MHD_KERNEL_TILED otherwise (the faster of each).
  * Never fails. */
 void mhd_config_default(mhd_config *cfg, int32_t nx, int32_t ny, int32_t nz,
                         int32_t precision);

@@ -193,7 +193,8 @@ void mhd_config_default(mhd_config* cfg, int32_t nx, int32_t ny, int32_t nz, int
     cfg->zeta = 0.0;
     cfg->eta = 5e-3;
     cfg->K = 5e-3;
-    cfg->kernel = MHD_KERNEL_SPLIT;
+    // the faster kernel of each precision at 512^3 on MI355X
+    cfg->kernel = precision == MHD_F64 ? MHD_KERNEL_SPLIT : MHD_KERNEL_TILED;
 }
 
 const char* mhd_strerror(int status)

@@ -392,10 +392,11 @@ __global__ __launch_bounds__(NTHR) void k_mse(const float* __restrict__ y,
     float acc = 0.0f;
     for (int64_t i = (int64_t)blockIdx.x * NTHR + threadIdx.x; i < count;
          i += (int64_t)gridDim.x * NTHR) {
+        // the scaled target is rounded before the difference (no fused multiply-add)
+#pragma clang fp contract(off)
         const int q = (int)(i & 7);
         const int64_t bc = i >> 3, b = bc >> logn3, cell = bc & (n3 - 1);
-        // the scaled target is rounded before the difference (no fused multiply-add)
-        const float d = y[i] - __fmul_rn(t[(b * 8 + q) * n3 + cell], tscale.v[q]);
+        const float d = y[i] - t[(b * 8 + q) * n3 + cell] * tscale.v[q];
         dy[i] = f2bf(scale * d);
         acc += d * d * inv;
     }

@@ -17,9 +17,14 @@
 //   M -> F (7 values):  ss, grad s, j x B.
 // With 512 threads per workgroup the FP64 ring (136 KB) still fits one
 // workgroup per CU, so every SIMD runs two waves instead of one; a wave
-// hides the LDS and barrier latency of the other.  The F -> M values live
-// in LDS past the ring; the M -> F values reuse the slot of plane t once
-// every wave has finished reading it.
+// hides the LDS and barrier latency of the other.  Both hand-overs use one
+// 20 KB area past the ring (M reads F's values, then writes its own into
+// the same entries of its cell), so a plane costs two workgroup barriers:
+//   derivatives of plane t; F writes its values
+//   -- barrier (plane t read, F's values visible) --
+//   plane t+4 goes into plane t's slot; M swaps the values
+//   -- barrier (plane t+4 and M's values visible) --
+//   physics, 2N update and stores of plane t; fetch plane t+5.
 #include <type_traits>
 
 #include "mhd_internal.hpp"
@@ -43,7 +48,15 @@ constexpr size_t ring_bytes() { return sizeof(typename Prec<PREC>::T) * NSLOT * 
 template <int PREC>
 constexpr size_t lds_bytes() { return ring_bytes<PREC>() + sizeof(typename Prec<PREC>::Rt) * NXF * NC; }
 
-static_assert(sizeof(double) * NXM * NC <= sizeof(double) * SLOT, "M->F values must fit one slot");
+static_assert(NXM <= NXF, "M's values reuse the entries of F's");
+
+// Workgroups per CU the kernel is built for: FP64's ring fills the LDS; the
+// FP32 rings would fit two, at half the registers per lane.
+#ifndef MHD_SPLIT_F32_BLOCKS
+#define MHD_SPLIT_F32_BLOCKS 1
+#endif
+template <int PREC>
+constexpr int blocks_per_cu() { return PREC == MHD_F64 ? 1 : MHD_SPLIT_F32_BLOCKS; }
 static_assert(NC % 64 == 0, "each group must be whole waves");
 
 struct TileMap {
@@ -79,7 +92,7 @@ __device__ __forceinline__ int tile_of_block(int b, const TileMap& m)
 }
 
 template <int PREC>
-__global__ __launch_bounds__(NTH, 1) void k_rk3_split(Grid g, const Phys* P_dev, Scales sc, TileMap map, int s,
+__global__ __launch_bounds__(NTH, blocks_per_cu<PREC>()) void k_rk3_split(Grid g, const Phys* P_dev, Scales sc, TileMap map, int s,
                                                      const typename Prec<PREC>::T* __restrict__ fin,
                                                      typename Prec<PREC>::T* __restrict__ fout,
                                                      typename Prec<PREC>::T* __restrict__ w,
@@ -91,7 +104,8 @@ __global__ __launch_bounds__(NTH, 1) void k_rk3_split(Grid g, const Phys* P_dev,
     using D2 = typename Prec<PREC>::D2;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* __restrict__ lds = reinterpret_cast<T*>(smem_raw);
-    Rt* __restrict__ xf = reinterpret_cast<Rt*>(smem_raw + ring_bytes<PREC>());  // [NXF][NC]
+    // exchange area past the ring: F's NXF values per cell, then (in place) M's NXM
+    Rt* __restrict__ xch = reinterpret_cast<Rt*>(smem_raw + ring_bytes<PREC>());  // [NXF][NC]
 
     const int tile = tile_of_block(blockIdx.x, map);
     if (tile == NO_TILE) return;  // the whole workgroup exits together
@@ -161,9 +175,12 @@ __global__ __launch_bounds__(NTH, 1) void k_rk3_split(Grid g, const Phys* P_dev,
             }
         };
 
-        const int cofs = (ly + R) * HX + (lx + R);
+        // V(slot, q, dy, dx): field q of the ring slot at offset (dx, dy) from the
+        // thread's cell.  Addressed from the cell's stencil corner so that every
+        // offset is a non-negative constant the LDS instructions take as an immediate.
+        const int corner = ly * HX + lx;  // cell (x - R, y - R) within a plane
         auto V = [&](int slot, int q, int dy, int dx) -> T {
-            return lds[slot * SLOT + q * PLANE + cofs + dy * HX + dx];
+            return lds[(slot * SLOT + corner) + (q * PLANE + (dy + R) * HX + (dx + R))];
         };
 
         // ---- z state of the group's fields: own-column history (t-3, t-2, t-1),
@@ -181,16 +198,21 @@ __global__ __launch_bounds__(NTH, 1) void k_rk3_split(Grid g, const Phys* P_dev,
         for (int c = 0; c < 3; ++c)
 #pragma unroll
             for (int k = 0; k < 3; ++k) past[c][k] = D2(0);
-        T wold[4] = {}, wnew[4] = {}, fnew[4] = {}, cc[4] = {};
+        T wold[4] = {}, cc[4] = {};
 
         auto cell_index = [&](int t) { return g.interior + t * g.mxy + (y0 + ly) * g.mx + (x0 + lx); };
 
         constexpr int SOFS = 8;
         load_plane(-3);
         for (int t = -7; t < g.nz; ++t) {
-            const bool out = t >= 0;  // uniform: warm-up planes only feed the z state
+            // warm-up planes (t < 0) run the whole computation too (branch-free
+            // code schedules better); only their z state is kept
             const int s0 = (t + SOFS) & 3;
-            if (t >= -3) {
+            const bool live = t >= -3;  // uniform: plane t is in the ring
+            Derivs<Rt> d;
+            T fc[4], wnew[4], fnew[4], cnew[4];
+            Rt S[3][3], divu = Rt(0), SS = Rt(0), B[3], J[3], jxB[3];
+            if (live) {
                 const int s1 = (t + 1 + SOFS) & 3, s2 = (t + 2 + SOFS) & 3, s3 = (t + 3 + SOFS) & 3;
                 const int sl[4] = {s0, s1, s2, s3};
 
@@ -239,11 +261,8 @@ __global__ __launch_bounds__(NTH, 1) void k_rk3_split(Grid g, const Phys* P_dev,
                         return dir == 0 ? D2(V(slot, q, 0, m)) - D2(V(slot, q, 0, -m))
                                         : D2(V(slot, q, m, 0)) - D2(V(slot, q, -m, 0));
                     };
-                    D2 res = D2(0);
-                    if (out) {
-                        res = D2(wm[0]) * dd(s1, 1) + D2(wm[1]) * dd(s2, 2) + D2(wm[2]) * dd(s3, 3);
-                        if (first_of_combo) res -= past[cb][0];
-                    }
+                    D2 res = D2(wm[0]) * dd(s1, 1) + D2(wm[1]) * dd(s2, 2) + D2(wm[2]) * dd(s3, 3);
+                    if (first_of_combo) res -= past[cb][0];
                     const D2 c1 = D2(wm[0]) * dd(s0, 1), c2 = D2(wm[1]) * dd(s0, 2),
                              c3 = D2(wm[2]) * dd(s0, 3);
                     if (first_of_combo) {
@@ -259,129 +278,107 @@ __global__ __launch_bounds__(NTH, 1) void k_rk3_split(Grid g, const Phys* P_dev,
                 };
 #define MHD_PHASE_FENCE() __builtin_amdgcn_sched_barrier(0)
 
-                Derivs<Rt> d;
                 if constexpr (G == 0) {
                     // ================= group F: lnrho, ux, uy, uz
                     D2 gdu[3] = {D2(0), D2(0), D2(0)};
-                    if (out) {
-                        d.lnrho = Rt(V(s0, 0, 0, 0));
-                        d.gl[0] = first(0, 0); d.gl[1] = first(0, 1); d.gl[2] = dz1(0, 0);
-                        D2 xx, yy, zz;
-                        second(0, 0, xx, yy, zz);
-                        d.lapl = Rt(xx + yy + zz);
-                    }
+                    d.lnrho = Rt(V(s0, 0, 0, 0));
+                    d.gl[0] = first(0, 0); d.gl[1] = first(0, 1); d.gl[2] = dz1(0, 0);
+                    D2 xx, yy, zz;
+                    second(0, 0, xx, yy, zz);
+                    d.lapl = Rt(xx + yy + zz);
                     MHD_PHASE_FENCE();
                     {
                         const D2 mz = mixed(1, 0, 2, true);
-                        if (out) {
-                            d.ux = Rt(V(s0, 1, 0, 0));
-                            d.gu[0][0] = first(1, 0); d.gu[0][1] = first(1, 1); d.gu[0][2] = dz1(1, 1);
-                            D2 xx, yy, zz;
-                            second(1, 1, xx, yy, zz);
-                            d.lapu[0] = Rt(xx + yy + zz);
-                            gdu[0] += xx;
-                            gdu[1] += dxy(1);
-                            gdu[2] += mz;
-                        }
+                        d.ux = Rt(V(s0, 1, 0, 0));
+                        d.gu[0][0] = first(1, 0); d.gu[0][1] = first(1, 1); d.gu[0][2] = dz1(1, 1);
+                        D2 xx, yy, zz;
+                        second(1, 1, xx, yy, zz);
+                        d.lapu[0] = Rt(xx + yy + zz);
+                        gdu[0] += xx;
+                        gdu[1] += dxy(1);
+                        gdu[2] += mz;
                     }
                     MHD_PHASE_FENCE();
                     {
                         const D2 mz = mixed(2, 1, 2, false);
-                        if (out) {
-                            d.uy = Rt(V(s0, 2, 0, 0));
-                            d.gu[1][0] = first(2, 0); d.gu[1][1] = first(2, 1); d.gu[1][2] = dz1(2, 2);
-                            D2 xx, yy, zz;
-                            second(2, 2, xx, yy, zz);
-                            d.lapu[1] = Rt(xx + yy + zz);
-                            gdu[1] += yy;
-                            gdu[0] += dxy(2);
-                            gdu[2] += mz;
-                        }
+                        d.uy = Rt(V(s0, 2, 0, 0));
+                        d.gu[1][0] = first(2, 0); d.gu[1][1] = first(2, 1); d.gu[1][2] = dz1(2, 2);
+                        D2 xx, yy, zz;
+                        second(2, 2, xx, yy, zz);
+                        d.lapu[1] = Rt(xx + yy + zz);
+                        gdu[1] += yy;
+                        gdu[0] += dxy(2);
+                        gdu[2] += mz;
                     }
                     MHD_PHASE_FENCE();
                     {
                         const D2 mx = mixed(3, 0, 0, true);
                         const D2 my = mixed(3, 1, 1, true);
-                        if (out) {
-                            d.uz = Rt(V(s0, 3, 0, 0));
-                            d.gu[2][0] = first(3, 0); d.gu[2][1] = first(3, 1); d.gu[2][2] = dz1(3, 3);
-                            D2 xx, yy, zz;
-                            second(3, 3, xx, yy, zz);
-                            d.lapu[2] = Rt(xx + yy + zz);
-                            gdu[2] += zz;
-                            gdu[0] += mx;
-                            gdu[1] += my;
-                        }
+                        d.uz = Rt(V(s0, 3, 0, 0));
+                        d.gu[2][0] = first(3, 0); d.gu[2][1] = first(3, 1); d.gu[2][2] = dz1(3, 3);
+                        D2 xx, yy, zz;
+                        second(3, 3, xx, yy, zz);
+                        d.lapu[2] = Rt(xx + yy + zz);
+                        gdu[2] += zz;
+                        gdu[0] += mx;
+                        gdu[1] += my;
                     }
                     MHD_PHASE_FENCE();
-                    if (out) {
 #pragma unroll
-                        for (int a = 0; a < 3; ++a) d.gdu[a] = Rt(gdu[a]);
-                    }
+                    for (int a = 0; a < 3; ++a) d.gdu[a] = Rt(gdu[a]);
                 } else {
                     // ================= group M: ss, Ax, Ay, Az
                     D2 jmu[3] = {D2(0), D2(0), D2(0)};
-                    if (out) {
-                        d.ss = Rt(V(s0, 4, 0, 0));
-                        d.gs[0] = first(4, 0); d.gs[1] = first(4, 1); d.gs[2] = dz1(4, 0);
-                        D2 xx, yy, zz;
-                        second(4, 0, xx, yy, zz);
-                        d.laps = Rt(xx + yy + zz);
-                    }
+                    d.ss = Rt(V(s0, 4, 0, 0));
+                    d.gs[0] = first(4, 0); d.gs[1] = first(4, 1); d.gs[2] = dz1(4, 0);
+                    D2 xx, yy, zz;
+                    second(4, 0, xx, yy, zz);
+                    d.laps = Rt(xx + yy + zz);
                     MHD_PHASE_FENCE();
                     {
                         const D2 mz = mixed(5, 0, 2, true);
-                        if (out) {
-                            d.dAx_dy = first(5, 1);
-                            d.dAx_dz = dz1(5, 1);
-                            D2 xx, yy, zz;
-                            second(5, 1, xx, yy, zz);
-                            d.lapA[0] = Rt(xx + yy + zz);
-                            jmu[0] -= yy + zz;
-                            jmu[1] += dxy(5);
-                            jmu[2] += mz;
-                        }
+                        d.dAx_dy = first(5, 1);
+                        d.dAx_dz = dz1(5, 1);
+                        D2 xx, yy, zz;
+                        second(5, 1, xx, yy, zz);
+                        d.lapA[0] = Rt(xx + yy + zz);
+                        jmu[0] -= yy + zz;
+                        jmu[1] += dxy(5);
+                        jmu[2] += mz;
                     }
                     MHD_PHASE_FENCE();
                     {
                         const D2 mz = mixed(6, 1, 2, false);
-                        if (out) {
-                            d.dAy_dx = first(6, 0);
-                            d.dAy_dz = dz1(6, 2);
-                            D2 xx, yy, zz;
-                            second(6, 2, xx, yy, zz);
-                            d.lapA[1] = Rt(xx + yy + zz);
-                            jmu[1] -= xx + zz;
-                            jmu[0] += dxy(6);
-                            jmu[2] += mz;
-                        }
+                        d.dAy_dx = first(6, 0);
+                        d.dAy_dz = dz1(6, 2);
+                        D2 xx, yy, zz;
+                        second(6, 2, xx, yy, zz);
+                        d.lapA[1] = Rt(xx + yy + zz);
+                        jmu[1] -= xx + zz;
+                        jmu[0] += dxy(6);
+                        jmu[2] += mz;
                     }
                     MHD_PHASE_FENCE();
                     {
                         const D2 mx = mixed(7, 0, 0, true);
                         const D2 my = mixed(7, 1, 1, true);
-                        if (out) {
-                            d.dAz_dx = first(7, 0);
-                            d.dAz_dy = first(7, 1);
-                            D2 xx, yy, zz;
-                            second(7, 3, xx, yy, zz);
-                            d.lapA[2] = Rt(xx + yy + zz);
-                            jmu[2] -= xx + yy;
-                            jmu[0] += mx;
-                            jmu[1] += my;
-                        }
+                        d.dAz_dx = first(7, 0);
+                        d.dAz_dy = first(7, 1);
+                        D2 xx, yy, zz;
+                        second(7, 3, xx, yy, zz);
+                        d.lapA[2] = Rt(xx + yy + zz);
+                        jmu[2] -= xx + yy;
+                        jmu[0] += mx;
+                        jmu[1] += my;
                     }
                     MHD_PHASE_FENCE();
-                    if (out) {
 #pragma unroll
-                        for (int a = 0; a < 3; ++a) d.jmu[a] = Rt(jmu[a]);
-                    }
+                    for (int a = 0; a < 3; ++a) d.jmu[a] = Rt(jmu[a]);
                 }
 #undef MHD_PHASE_FENCE
 
                 // centre values of the group's fields (the 2N update's f_in) and
                 // the history shift, both before plane t's slot is reused
-                T fc[4];
 #pragma unroll
                 for (int k4 = 0; k4 < 4; ++k4) {
                     fc[k4] = V(s0, q0 + k4, 0, 0);
@@ -390,70 +387,70 @@ __global__ __launch_bounds__(NTH, 1) void k_rk3_split(Grid g, const Phys* P_dev,
                     hist[2][k4] = fc[k4];
                 }
 
-                if (out) {
-                    // the physics constants are read here, per plane, from device
-                    // memory (scalar loads) rather than held in scalar registers
-                    // across the march, which would spill
+                if constexpr (G == 0) {
+                    shear(d.gu, S, divu, SS);
+                    const Rt v[NXF] = {d.lnrho, d.ux, d.uy, d.uz, d.gl[0], d.gl[1], d.gl[2],
+                                       d.lapl, SS, divu};
+#pragma unroll
+                    for (int i = 0; i < NXF; ++i) xch[i * NC + tid] = v[i];
+                } else {
                     const Phys P = *P_dev;
-                    Rt S[3][3], divu = Rt(0), SS = Rt(0), B[3], J[3], jxB[3];
-                    if constexpr (G == 0) {
-                        shear(d.gu, S, divu, SS);
-                        const Rt v[NXF] = {d.lnrho, d.ux, d.uy, d.uz, d.gl[0], d.gl[1], d.gl[2],
-                                           d.lapl, SS, divu};
-#pragma unroll
-                        for (int i = 0; i < NXF; ++i) xf[i * NC + tid] = v[i];
-                    } else {
-                        magnetic(d, P, B, J, jxB);
-                    }
-                    __syncthreads();  // every read of plane t's slot is done
-                    Rt* __restrict__ xm = reinterpret_cast<Rt*>(lds + s0 * SLOT);  // [NXM][NC]
-                    if constexpr (G == 1) {
-                        const Rt v[NXM] = {d.ss, d.gs[0], d.gs[1], d.gs[2], jxB[0], jxB[1], jxB[2]};
-#pragma unroll
-                        for (int i = 0; i < NXM; ++i) xm[i * NC + tid] = v[i];
-                    }
-                    __syncthreads();  // exchanged values visible
-                    Rt rhs[4];
-                    if constexpr (G == 0) {
-                        d.ss = xm[0 * NC + tid];
-#pragma unroll
-                        for (int a = 0; a < 3; ++a) {
-                            d.gs[a] = xm[(1 + a) * NC + tid];
-                            jxB[a] = xm[(4 + a) * NC + tid];
-                        }
-                        rhs_flow(d, P, S, divu, jxB, rhs);
-                    } else {
-                        d.lnrho = xf[0 * NC + tid];
-                        d.ux = xf[1 * NC + tid];
-                        d.uy = xf[2 * NC + tid];
-                        d.uz = xf[3 * NC + tid];
-#pragma unroll
-                        for (int a = 0; a < 3; ++a) d.gl[a] = xf[(4 + a) * NC + tid];
-                        d.lapl = xf[7 * NC + tid];
-                        SS = xf[8 * NC + tid];
-                        divu = xf[9 * NC + tid];
-                        rhs_entropy_induction(d, P, divu, SS, B, J, rhs);
-                    }
-#pragma unroll
-                    for (int k4 = 0; k4 < 4; ++k4)
-                        rk_values<PREC>(s, fc[k4], wold[k4], rhs[k4], dt, wnew[k4], fnew[k4], cc[k4]);
+                    magnetic(d, P, B, J, jxB);
                 }
             }
 
-            // ---- plane t+4 replaces plane t in the ring (after every read of the
-            // exchanged values in that slot); this plane's results go out; plane
-            // t+5 and the next plane's register values are fetched
+            // Every read of plane t is done and F's values are visible: plane
+            // t+4 replaces plane t in the ring, and M takes F's values and puts
+            // its own in their place (each thread only touches the entries of
+            // its own cell, so program order separates the read and the write).
             __syncthreads();
             store_plane((t + 4 + SOFS) & 3);
-            if (t >= 0 && active) {
-                const unsigned c = (unsigned)cell_index(t);
+            if constexpr (G == 1) {
+                if (live) {
+                    d.lnrho = xch[0 * NC + tid];
+                    d.ux = xch[1 * NC + tid];
+                    d.uy = xch[2 * NC + tid];
+                    d.uz = xch[3 * NC + tid];
 #pragma unroll
-                for (int k4 = 0; k4 < 4; ++k4) {
-                    *at(field_ptr(w, q0 + k4), c) = wnew[k4];
-                    *at(field_ptr(fout, q0 + k4), c) = fnew[k4];
-                    if constexpr (PREC == MHD_F32C) *at(field_ptr(comp, q0 + k4), c) = cc[k4];
+                    for (int a = 0; a < 3; ++a) d.gl[a] = xch[(4 + a) * NC + tid];
+                    d.lapl = xch[7 * NC + tid];
+                    SS = xch[8 * NC + tid];
+                    divu = xch[9 * NC + tid];
+                    const Rt v[NXM] = {d.ss, d.gs[0], d.gs[1], d.gs[2], jxB[0], jxB[1], jxB[2]};
+#pragma unroll
+                    for (int i = 0; i < NXM; ++i) xch[i * NC + tid] = v[i];
                 }
             }
+            __syncthreads();  // plane t+4 and M's values visible
+
+            if (live) {
+                // the physics constants are read here, per plane, from device
+                // memory (scalar loads) rather than held in scalar registers
+                // across the march, which would spill
+                const Phys P = *P_dev;
+                Rt rhs[4];
+                if constexpr (G == 0) {
+                    d.ss = xch[0 * NC + tid];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        d.gs[a] = xch[(1 + a) * NC + tid];
+                        jxB[a] = xch[(4 + a) * NC + tid];
+                    }
+                    rhs_flow(d, P, S, divu, jxB, rhs);
+                } else {
+                    rhs_entropy_induction(d, P, divu, SS, B, J, rhs);
+                }
+#pragma unroll
+                for (int k4 = 0; k4 < 4; ++k4) {
+                    cnew[k4] = cc[k4];
+                    rk_values<PREC>(s, fc[k4], wold[k4], rhs[k4], dt, wnew[k4], fnew[k4], cnew[k4]);
+                }
+            }
+
+            // plane t+5 and the next plane's register values are fetched before
+            // this plane's results go out: the vector-memory counter covers loads
+            // and stores alike in issue order, so the next plane's waits for the
+            // loads do not also wait for these stores
             if (t + 5 <= g.nz + 2) load_plane(t + 5);
             if (active && t + 1 >= 0 && t + 1 < g.nz) {
                 const unsigned c = (unsigned)cell_index(t + 1);
@@ -466,7 +463,15 @@ __global__ __launch_bounds__(NTH, 1) void k_rk3_split(Grid g, const Phys* P_dev,
                     for (int k4 = 0; k4 < 4; ++k4) cc[k4] = *at(field_ptr(comp, q0 + k4), c);
                 }
             }
-            __syncthreads();  // plane t+4 visible to every wave
+            if (t >= 0 && active) {
+                const unsigned c = (unsigned)cell_index(t);
+#pragma unroll
+                for (int k4 = 0; k4 < 4; ++k4) {
+                    *at(field_ptr(w, q0 + k4), c) = wnew[k4];
+                    *at(field_ptr(fout, q0 + k4), c) = fnew[k4];
+                    if constexpr (PREC == MHD_F32C) *at(field_ptr(comp, q0 + k4), c) = cnew[k4];
+                }
+            }
         }
     };
     if (grp == 0)

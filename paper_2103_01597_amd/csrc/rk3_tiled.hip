@@ -177,9 +177,12 @@ __global__ __launch_bounds__(NT, blocks_per_cu<PREC>()) void k_rk3_tiled(Grid g,
         }
     };
 
-    const int cofs = (ly + R) * HX + (lx + R);  // own cell within a plane
+    // V(slot, q, dy, dx): field q of the ring slot at offset (dx, dy) from the
+    // thread's cell.  Addressed from the cell's stencil corner so that every
+    // offset is a non-negative constant the LDS instructions take as an immediate.
+    const int corner = ly * HX + lx;  // cell (x - R, y - R) within a plane
     auto V = [&](int slot, int q, int dy, int dx) -> T {
-        return lds[slot * SLOT + q * PLANE + cofs + dy * HX + dx];
+        return lds[(slot * SLOT + corner) + (q * PLANE + (dy + R) * HX + (dx + R))];
     };
 
     // ---- z state: own-column history (planes t-3, t-2, t-1) and the past
@@ -196,7 +199,9 @@ __global__ __launch_bounds__(NT, blocks_per_cu<PREC>()) void k_rk3_tiled(Grid g,
     for (int c = 0; c < 6; ++c)
 #pragma unroll
         for (int k = 0; k < 3; ++k) past[c][k] = D2(0);
-    T wold[NQ] = {}, wnew[NQ] = {}, fnew[NQ] = {}, cc[NQ] = {};
+    // wold, cc: the 2N register and compensation of the next plane, fetched a
+    // plane ahead; wnew, fnew, cnew: this plane's results
+    T wold[NQ] = {}, wnew[NQ] = {}, fnew[NQ] = {}, cc[NQ] = {}, cnew[NQ] = {};
 
     auto cell_index = [&](int t) { return g.interior + t * g.mxy + (y0 + ly) * g.mx + (x0 + lx); };
 
@@ -207,7 +212,8 @@ __global__ __launch_bounds__(NT, blocks_per_cu<PREC>()) void k_rk3_tiled(Grid g,
             const int s0 = (t + SOFS) & 3, s1 = (t + 1 + SOFS) & 3, s2 = (t + 2 + SOFS) & 3,
                       s3 = (t + 3 + SOFS) & 3;
             const int sl[4] = {s0, s1, s2, s3};
-            const bool out = t >= 0;  // uniform: warm-up planes only feed the z state
+            // warm-up planes (t < 0) run the whole computation too (branch-free
+            // code schedules better); only their z state is kept
 
             Derivs<Rt> d;
             D2 gdu[3] = {D2(0), D2(0), D2(0)}, jmu[3] = {D2(0), D2(0), D2(0)};
@@ -259,11 +265,8 @@ __global__ __launch_bounds__(NT, blocks_per_cu<PREC>()) void k_rk3_tiled(Grid g,
                     return dir == 0 ? D2(V(slot, q, 0, m)) - D2(V(slot, q, 0, -m))
                                     : D2(V(slot, q, m, 0)) - D2(V(slot, q, -m, 0));
                 };
-                D2 res = D2(0);
-                if (out) {
-                    res = D2(wm[0]) * dd(s1, 1) + D2(wm[1]) * dd(s2, 2) + D2(wm[2]) * dd(s3, 3);
-                    if (first_of_combo) res -= past[cb][0];
-                }
+                D2 res = D2(wm[0]) * dd(s1, 1) + D2(wm[1]) * dd(s2, 2) + D2(wm[2]) * dd(s3, 3);
+                if (first_of_combo) res -= past[cb][0];
                 const D2 c1 = D2(wm[0]) * dd(s0, 1), c2 = D2(wm[1]) * dd(s0, 2),
                          c3 = D2(wm[2]) * dd(s0, 3);
                 if (first_of_combo) {
@@ -281,7 +284,7 @@ __global__ __launch_bounds__(NT, blocks_per_cu<PREC>()) void k_rk3_tiled(Grid g,
     if constexpr (((FENCE_MASK >> (i)) & 1) != 0) __builtin_amdgcn_sched_barrier(0)
 
             // ---- lnrho
-            if (out) {
+            {
                 d.lnrho = Rt(V(s0, 0, 0, 0));
                 d.gl[0] = first(0, 0); d.gl[1] = first(0, 1); d.gl[2] = dz1(0);
                 D2 xx, yy, zz;
@@ -290,7 +293,7 @@ __global__ __launch_bounds__(NT, blocks_per_cu<PREC>()) void k_rk3_tiled(Grid g,
             }
             MHD_PHASE_FENCE(0);
             // ---- ss
-            if (out) {
+            {
                 d.ss = Rt(V(s0, 4, 0, 0));
                 d.gs[0] = first(4, 0); d.gs[1] = first(4, 1); d.gs[2] = dz1(4);
                 D2 xx, yy, zz;
@@ -301,108 +304,96 @@ __global__ __launch_bounds__(NT, blocks_per_cu<PREC>()) void k_rk3_tiled(Grid g,
             // ---- ux: grad, lap; D_xx ux -> gdu_x, D_xy ux -> gdu_y, D_xz ux -> gdu_z
             {
                 const D2 mz = mixed(1, 0, 2, true);
-                if (out) {
-                    d.ux = Rt(V(s0, 1, 0, 0));
-                    d.gu[0][0] = first(1, 0); d.gu[0][1] = first(1, 1); d.gu[0][2] = dz1(1);
-                    D2 xx, yy, zz;
-                    second(1, xx, yy, zz);
-                    d.lapu[0] = Rt(xx + yy + zz);
-                    gdu[0] += xx;
-                    gdu[1] += dxy(1);
-                    gdu[2] += mz;
-                }
+                d.ux = Rt(V(s0, 1, 0, 0));
+                d.gu[0][0] = first(1, 0); d.gu[0][1] = first(1, 1); d.gu[0][2] = dz1(1);
+                D2 xx, yy, zz;
+                second(1, xx, yy, zz);
+                d.lapu[0] = Rt(xx + yy + zz);
+                gdu[0] += xx;
+                gdu[1] += dxy(1);
+                gdu[2] += mz;
             }
             MHD_PHASE_FENCE(2);
             // ---- uy
             {
                 const D2 mz = mixed(2, 1, 2, false);
-                if (out) {
-                    d.uy = Rt(V(s0, 2, 0, 0));
-                    d.gu[1][0] = first(2, 0); d.gu[1][1] = first(2, 1); d.gu[1][2] = dz1(2);
-                    D2 xx, yy, zz;
-                    second(2, xx, yy, zz);
-                    d.lapu[1] = Rt(xx + yy + zz);
-                    gdu[1] += yy;
-                    gdu[0] += dxy(2);
-                    gdu[2] += mz;
-                }
+                d.uy = Rt(V(s0, 2, 0, 0));
+                d.gu[1][0] = first(2, 0); d.gu[1][1] = first(2, 1); d.gu[1][2] = dz1(2);
+                D2 xx, yy, zz;
+                second(2, xx, yy, zz);
+                d.lapu[1] = Rt(xx + yy + zz);
+                gdu[1] += yy;
+                gdu[0] += dxy(2);
+                gdu[2] += mz;
             }
             MHD_PHASE_FENCE(3);
             // ---- uz
             {
                 const D2 mx = mixed(3, 0, 0, true);
                 const D2 my = mixed(3, 1, 1, true);
-                if (out) {
-                    d.uz = Rt(V(s0, 3, 0, 0));
-                    d.gu[2][0] = first(3, 0); d.gu[2][1] = first(3, 1); d.gu[2][2] = dz1(3);
-                    D2 xx, yy, zz;
-                    second(3, xx, yy, zz);
-                    d.lapu[2] = Rt(xx + yy + zz);
-                    gdu[2] += zz;
-                    gdu[0] += mx;
-                    gdu[1] += my;
-                }
+                d.uz = Rt(V(s0, 3, 0, 0));
+                d.gu[2][0] = first(3, 0); d.gu[2][1] = first(3, 1); d.gu[2][2] = dz1(3);
+                D2 xx, yy, zz;
+                second(3, xx, yy, zz);
+                d.lapu[2] = Rt(xx + yy + zz);
+                gdu[2] += zz;
+                gdu[0] += mx;
+                gdu[1] += my;
             }
             MHD_PHASE_FENCE(4);
             // ---- Ax: mu0 j_x gets -(D_yy + D_zz) Ax, j_y gets D_xy Ax, j_z gets D_xz Ax
             {
                 const D2 mz = mixed(5, 0, 5, true);
-                if (out) {
-                    d.dAx_dy = first(5, 1);
-                    d.dAx_dz = dz1(5);
-                    D2 xx, yy, zz;
-                    second(5, xx, yy, zz);
-                    d.lapA[0] = Rt(xx + yy + zz);
-                    jmu[0] -= yy + zz;
-                    jmu[1] += dxy(5);
-                    jmu[2] += mz;
-                }
+                d.dAx_dy = first(5, 1);
+                d.dAx_dz = dz1(5);
+                D2 xx, yy, zz;
+                second(5, xx, yy, zz);
+                d.lapA[0] = Rt(xx + yy + zz);
+                jmu[0] -= yy + zz;
+                jmu[1] += dxy(5);
+                jmu[2] += mz;
             }
             MHD_PHASE_FENCE(5);
             // ---- Ay
             {
                 const D2 mz = mixed(6, 1, 5, false);
-                if (out) {
-                    d.dAy_dx = first(6, 0);
-                    d.dAy_dz = dz1(6);
-                    D2 xx, yy, zz;
-                    second(6, xx, yy, zz);
-                    d.lapA[1] = Rt(xx + yy + zz);
-                    jmu[1] -= xx + zz;
-                    jmu[0] += dxy(6);
-                    jmu[2] += mz;
-                }
+                d.dAy_dx = first(6, 0);
+                d.dAy_dz = dz1(6);
+                D2 xx, yy, zz;
+                second(6, xx, yy, zz);
+                d.lapA[1] = Rt(xx + yy + zz);
+                jmu[1] -= xx + zz;
+                jmu[0] += dxy(6);
+                jmu[2] += mz;
             }
             MHD_PHASE_FENCE(6);
             // ---- Az
             {
                 const D2 mx = mixed(7, 0, 3, true);
                 const D2 my = mixed(7, 1, 4, true);
-                if (out) {
-                    d.dAz_dx = first(7, 0);
-                    d.dAz_dy = first(7, 1);
-                    D2 xx, yy, zz;
-                    second(7, xx, yy, zz);
-                    d.lapA[2] = Rt(xx + yy + zz);
-                    jmu[2] -= xx + yy;
-                    jmu[0] += mx;
-                    jmu[1] += my;
-                }
+                d.dAz_dx = first(7, 0);
+                d.dAz_dy = first(7, 1);
+                D2 xx, yy, zz;
+                second(7, xx, yy, zz);
+                d.lapA[2] = Rt(xx + yy + zz);
+                jmu[2] -= xx + yy;
+                jmu[0] += mx;
+                jmu[1] += my;
             }
             MHD_PHASE_FENCE(7);
 #undef MHD_PHASE_FENCE
 
-            if (out) {
 #pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    d.gdu[a] = Rt(gdu[a]);
-                    d.jmu[a] = Rt(jmu[a]);
-                }
-                Rt rhs[NQ];
-                rhs_physics<Rt>(d, P, rhs);
+            for (int a = 0; a < 3; ++a) {
+                d.gdu[a] = Rt(gdu[a]);
+                d.jmu[a] = Rt(jmu[a]);
+            }
+            Rt rhs[NQ];
+            rhs_physics<Rt>(d, P, rhs);
 #pragma unroll
-                for (int q = 0; q < NQ; ++q)
-                    rk_values<PREC>(s, V(s0, q, 0, 0), wold[q], rhs[q], dt, wnew[q], fnew[q], cc[q]);
+            for (int q = 0; q < NQ; ++q) {
+                cnew[q] = cc[q];
+                rk_values<PREC>(s, V(s0, q, 0, 0), wold[q], rhs[q], dt, wnew[q], fnew[q], cnew[q]);
             }
 
             // ---- advance the own-column history past plane t
@@ -414,22 +405,13 @@ __global__ __launch_bounds__(NT, blocks_per_cu<PREC>()) void k_rk3_tiled(Grid g,
             }
         }
 
-        // ---- plane t+4 replaces plane t in the ring; then this plane's results
-        // go out, then plane t+5 and the next plane's register values are
-        // fetched.  This order keeps every wait on the vector-memory counter
-        // (which covers loads and stores alike, in issue order) behind
-        // operations issued a whole iteration earlier.
+        // ---- plane t+4 replaces plane t in the ring; then plane t+5 and the
+        // next plane's register values are fetched, and only then do this
+        // plane's results go out.  The vector-memory counter covers loads and
+        // stores alike in issue order, so with the loads first the next
+        // plane's waits for them do not also wait for these stores.
         __syncthreads();  // every read of plane t is done
         store_plane((t + 4 + SOFS) & 3);
-        if (t >= 0 && active) {
-            const unsigned c = (unsigned)cell_index(t);
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                *at(field_ptr(w, q), c) = wnew[q];
-                *at(field_ptr(fout, q), c) = fnew[q];
-                if constexpr (PREC == MHD_F32C) *at(field_ptr(comp, q), c) = cc[q];
-            }
-        }
         if (t + 5 <= g.nz + 2) load_plane(t + 5);
         if (active && t + 1 >= 0 && t + 1 < g.nz) {
             const unsigned c = (unsigned)cell_index(t + 1);
@@ -440,6 +422,15 @@ __global__ __launch_bounds__(NT, blocks_per_cu<PREC>()) void k_rk3_tiled(Grid g,
             if constexpr (PREC == MHD_F32C) {
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) cc[q] = *at(field_ptr(comp, q), c);
+            }
+        }
+        if (t >= 0 && active) {
+            const unsigned c = (unsigned)cell_index(t);
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                *at(field_ptr(w, q), c) = wnew[q];
+                *at(field_ptr(fout, q), c) = fnew[q];
+                if constexpr (PREC == MHD_F32C) *at(field_ptr(comp, q), c) = cnew[q];
             }
         }
         __syncthreads();  // plane t+4 visible to every wave

@@ -102,11 +102,13 @@ class Solver:
     :meth:`grid_view` / :meth:`interior_view` for (8, mz, my, mx) views.
     """
 
-    def __init__(self, nx, ny, nz, precision="f64", kernel="split", **phys):
+    def __init__(self, nx, ny, nz, precision="f64", kernel=None, **phys):
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         cfg = Config()
         lib().mhd_config_default(ctypes.byref(cfg), nx, ny, nz, self.precision)
-        cfg.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+        if kernel is not None:  # None: the library's default for the precision
+            cfg.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+        self.kernel = {v: k for k, v in KERNELS.items()}[cfg.kernel]
         for k, v in phys.items():
             if k == "bext":
                 cfg.bext = (ctypes.c_double * 3)(*[float(b) for b in v])

@@ -49,8 +49,10 @@ def test_strerror_and_defaults(L):
     assert (cfg.nx, cfg.ny, cfg.nz, cfg.precision) == (32, 16, 8, 1)
     assert cfg.gamma == 5.0 / 3.0 and cfg.nu == 5e-3 and cfg.eta == 5e-3 and cfg.K == 5e-3
     assert cfg.cs0 == 1.0 and cfg.cp == 1.0 and cfg.mu0 == 1.0 and cfg.zeta == 0.0
-    assert cfg.kernel == 2 and cfg.reserved_ == 0  # MHD_KERNEL_SPLIT
+    assert cfg.kernel == 0 and cfg.reserved_ == 0  # MHD_KERNEL_TILED for FP32C
     assert abs(cfg.lx - 6.283185307179586) < 1e-15 and list(cfg.bext) == [0.0, 0.0, 0.0]
+    L.mhd_config_default(ctypes.byref(cfg), 8, 8, 8, mhd.F64)
+    assert cfg.kernel == 2  # MHD_KERNEL_SPLIT for FP64
 
 
 def _init(L, **kw):

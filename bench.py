@@ -37,6 +37,8 @@ WORKLOAD_TEXT = {
                "dt 1e-3, halo fill every substep",
     "sub256": "sub256: 256^3 periodic, 8 fields, 1e-2 x 4 Fourier modes |k|<=8 seed 2, "
               "dt 1e-3, halo fill every substep",
+    "w0_512": "w0: 512^3 periodic, 8 fields i.i.d. U[0,1) (the paper's benchmark state), "
+              "dt 2^-23, halo fill every substep",
     "large1024x512x512": "large: 1024x512x512 periodic (4pi x 2pi x 2pi), u modes |k|<=16 "
                          "amp 0.1, A amp 1e-3, seed 4, dt 1e-3, halo fill every substep",
 }
@@ -163,7 +165,7 @@ def main():
                     help="comma list of f64, f32c, f32 (default: f64,f32c; f32c for "
                          "the large workload)")
     ap.add_argument("--workload", default="prec512",
-                    choices=["prec512", "sub256", "large1024x512x512"])
+                    choices=["prec512", "sub256", "w0_512", "large1024x512x512"])
     ap.add_argument("--kernel", default=None, choices=["split", "tiled", "direct"],
                     help="fused-substep kernel (default: the library's default for each "
                          "precision: split for f64, tiled otherwise)")
@@ -197,6 +199,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(r["ms_per_step"], 4),
+        "ns_per_cell_step": round(r["ms_per_step"] * 1e6 / math.prod(wl["shape"]), 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -122,7 +122,9 @@ void mhd_config_default(mhd_config *cfg, int32_t nx, int32_t ny, int32_t nz,
 /* Validate *cfg, bind the current HIP device and create a context.
  * Writes the buffer geometry to *layout.  *out stays NULL on failure.
  * Errors: MHD_ERR_INVALID (NULL argument, n_i < 1, a padded field of more
- * than 2^31 - 4096 cells, non-finite or non-positive lengths, gamma <= 1,
+ * than 2^31 - 4096 cells or of 4 GiB or more (the kernels address within a
+ * field with 32-bit offsets), ny or nz above 65535, non-finite or
+ * non-positive lengths, gamma <= 1,
  * cp <= 0, mu0 == 0, unknown precision or kernel, reserved_ != 0),
  * MHD_ERR_NO_DEVICE, MHD_ERR_DEVICE, MHD_ERR_NOMEM. */
 int mhd_init(const mhd_config *cfg, mhd_ctx **out, mhd_layout *layout);

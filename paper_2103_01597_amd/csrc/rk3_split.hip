@@ -33,7 +33,10 @@
 namespace mhd {
 namespace {
 
-constexpr int TX = 32, TY = 8, NC = TX * TY;  // cells per tile plane
+#ifndef MHD_SPLIT_TX
+#define MHD_SPLIT_TX 32
+#endif
+constexpr int TX = MHD_SPLIT_TX, TY = 256 / MHD_SPLIT_TX, NC = TX * TY;  // cells per tile plane
 constexpr int NTH = 2 * NC;                    // threads: two groups of NC
 constexpr int HX = TX + 2 * R, HY = TY + 2 * R, PLANE = HX * HY;  // 38 x 14 = 532
 constexpr int SLOT = NQ * PLANE;

@@ -98,6 +98,8 @@ WORKLOADS = {
     "oracle32": dict(shape=(32, 32, 32), kmax=3, amp=1e-2, seed=1, dt=1e-3, steps=1),
     "sub256": dict(shape=(256, 256, 256), kmax=8, amp=1e-2, seed=2, dt=1e-3, steps=100),
     "prec512": dict(shape=(512, 512, 512), kmax=8, amp=1e-2, seed=3, dt=1e-3, steps=100),
+    # the paper's own benchmark state (Section 5): i.i.d. U[0, 1) fields, dt = 2^-23
+    "w0_512": dict(shape=(512, 512, 512), init="uniform01", seed=0, dt=2.0 ** -23, steps=100),
     "large1024x512x512": dict(shape=(1024, 512, 512), kmax=16,
                               amp=(0.0, 0.1, 0.1, 0.1, 0.0, 1e-3, 1e-3, 1e-3),
                               seed=4, dt=1e-3, steps=50,
@@ -108,12 +110,25 @@ WORKLOADS = {
 def workload_state(name: str, dtype=np.float64, shape=None) -> np.ndarray:
     """Initial state of a named workload (optionally on another grid shape)."""
     w = WORKLOADS[name]
+    if w.get("init") == "uniform01":
+        return uniform01(shape or w["shape"], w["seed"], dtype=dtype)
     return fourier_modes(shape or w["shape"], w["kmax"], w["amp"], w["seed"],
                          lengths=w.get("lengths", (2 * math.pi,) * 3), dtype=dtype)
+
+
+def uniform01_fields(shape, seed):
+    """The fields of ``uniform01`` one at a time, (q, (nz, ny, nx) array);
+    bit-identical to ``uniform01`` (the same generator stream, in order)."""
+    nx, ny, nz = shape
+    rng = np.random.default_rng(seed)
+    for q in range(NQ):
+        yield q, rng.random((nz, ny, nx))
 
 
 def workload_fields(name: str, shape=None):
     """``workload_state`` one field at a time (see ``fourier_mode_fields``)."""
     w = WORKLOADS[name]
+    if w.get("init") == "uniform01":
+        return uniform01_fields(shape or w["shape"], w["seed"])
     return fourier_mode_fields(shape or w["shape"], w["kmax"], w["amp"], w["seed"],
                                lengths=w.get("lengths", (2 * math.pi,) * 3))

@@ -53,7 +53,26 @@ BYTES_PER_CELL = {
 }
 
 
-def run_precision(mhd, inputs, torch, name, prec, steps, warmup, kernel):
+def time_segmented(S, torch, bufs, cur, w, comp, dt, steps, cells):
+    """The same steps through mhd_step_segmented (inner box on the launch
+    stream, packed halo exchange on a second stream, outer shell after it)."""
+    comm = torch.cuda.Stream()
+    send, recv = S.segment_buffer(), S.segment_buffer()
+    stream = torch.cuda.current_stream()
+    cur = S.step_segmented(bufs, cur, w, comp, dt, 1, send, recv, comm_stream=comm)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    cur = S.step_segmented(bufs, cur, w, comp, dt, steps, send, recv, comm_stream=comm)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    return dict(ms_per_step=round(ms / steps, 4),
+                gcups=round(3 * cells * steps / (ms * 1e-3) / 1e9, 4))
+
+
+def run_precision(mhd, inputs, torch, name, prec, steps, warmup, kernel, segmented=False):
     wl = inputs.WORKLOADS[name]
     n = wl["shape"]
     cells = n[0] * n[1] * n[2]
@@ -90,6 +109,7 @@ def run_precision(mhd, inputs, torch, name, prec, steps, warmup, kernel):
     alg_bytes = steps * cells * sum(BYTES_PER_CELL[prec])
     achieved = alg_bytes / (sum_kern_ms * 1e-3) / 1e9
     nonfinite = S.reduce(bufs[cur], 0, "nonfinite")
+    seg = time_segmented(S, torch, bufs, cur, w, comp, dt, steps, cells) if segmented else None
     res = dict(
         gcups=3 * cells * steps / (total_ms * 1e-3) / 1e9,
         ms_per_step=total_ms / steps,
@@ -100,6 +120,7 @@ def run_precision(mhd, inputs, torch, name, prec, steps, warmup, kernel):
         kernel_gcups=3 * cells * steps / (sum_kern_ms * 1e-3) / 1e9,
         nonfinite=nonfinite,
         kernel=kernel,
+        segmented=seg,
     )
     S.close()
     del bufs, w, comp
@@ -166,6 +187,9 @@ def main():
                          "the large workload)")
     ap.add_argument("--workload", default="prec512",
                     choices=["prec512", "sub256", "w0_512", "large1024x512x512"])
+    ap.add_argument("--no-segmented", action="store_true",
+                    help="skip the timing of the segmented (inner/outer, packed halo "
+                         "exchange) step")
     ap.add_argument("--kernel", default=None, choices=["split", "tiled", "direct"],
                     help="fused-substep kernel (default: the library's default for each "
                          "precision: split for f64, tiled otherwise)")
@@ -185,7 +209,7 @@ def main():
     results = {}
     for prec in args.precisions.split(","):
         results[prec] = run_precision(mhd, inputs, torch, args.workload, prec, args.steps,
-                                      args.warmup, args.kernel)
+                                      args.warmup, args.kernel, not args.no_segmented)
         print(f"# {prec}: {json.dumps(results[prec])}", file=sys.stderr, flush=True)
 
     main_prec = "f64" if "f64" in results else next(iter(results))
@@ -221,6 +245,9 @@ def main():
             line[f"{prec}_kernel_ms_avg"] = round(rr["kernel_ms_avg"], 4)
             line[f"{prec}_kernel"] = KERNEL_SYMBOL[rr["kernel"]]
             line[f"{prec}_traffic"] = measured_traffic(rr["kernel"], prec, args.workload)
+    segs = {prec: rr["segmented"] for prec, rr in results.items() if rr["segmented"]}
+    if segs:
+        line["segmented"] = segs
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(inputs, inputs.WORKLOADS["prec512"])
     print(json.dumps(line), flush=True)

@@ -109,6 +109,12 @@ typedef struct mhd_layout {
 
 typedef struct mhd_ctx mhd_ctx;
 
+/* A sub-box of the interior in interior cell indices, half-open:
+ * x0 <= x < x1, y0 <= y < y1, z0 <= z < z1 (0 <= x0 <= x1 <= nx, ...). */
+typedef struct mhd_box {
+    int32_t x0, x1, y0, y1, z0, z1;
+} mhd_box;
+
 /* ------------------------------------------------------------ functions */
 
 /* Fill *cfg with the defaults for an n = (nx, ny, nz) grid: l = 2*pi per
@@ -162,6 +168,63 @@ int mhd_rk3_substep(mhd_ctx *ctx, int32_t s, const void *f_in, void *f_out, void
  * MHD_ERR_INVALID for nsteps < 0 or *cur not in {0, 1}. */
 int mhd_step(mhd_ctx *ctx, void *const f[2], int32_t *cur, void *w, void *comp, double dt,
              int32_t nsteps, void *stream);
+
+/* ------------------------------------------------ segmented iteration
+ * The iteration of Section 3.3 (Fig. iteration): pack the 6 side and 12
+ * edge segments of the 3-cell boundary layer (corners are not needed by
+ * the stencil, Section 5) into a send buffer, exchange them with the
+ * neighbouring subdomains while the inner box (cells at least 3 from every
+ * face, which read no halo) is updated, unpack the received segments into
+ * the halo, then update the outer shell.  On one GPU with periodic
+ * boundaries the neighbour in every direction is the subdomain itself, so
+ * the exchange is a device-to-device copy of each segment to the slot of
+ * the opposite direction (where several GPUs would exchange peer to peer).
+ * Every entry point here requires nx, ny, nz >= 3 (else MHD_ERR_INVALID). */
+
+/* Elements of one packed buffer (all 8 fields, 18 segments; bytes =
+ * elements * layout.elem_size).  Segment order: directions d in
+ * {-1,0,1}^3 with one or two non-zero components, z slowest then y then x;
+ * each segment [field][z][y][x] over its extents (3 along every non-zero
+ * component of d, n along the others).  -1 for a NULL ctx. */
+int64_t mhd_halo_segment_elems(const mhd_ctx *ctx);
+
+/* Pack the boundary layer of `fields` (interior cells within 3 of the face
+ * or edge in direction d, for every segment d) into `sendbuf` (device,
+ * mhd_halo_segment_elems elements of the storage type). */
+int mhd_halo_pack(mhd_ctx *ctx, const void *fields, void *sendbuf, void *stream);
+
+/* Scatter received segments into the halo of `fields`: segment d of
+ * `recvbuf` fills the halo cells beyond the face or edge in direction d. */
+int mhd_halo_unpack(mhd_ctx *ctx, const void *recvbuf, void *fields, void *stream);
+
+/* Pack, the periodic one-GPU exchange (received segment d = sent segment
+ * -d) and unpack, on `stream`: afterwards every side and edge halo cell of
+ * `fields` equals what mhd_halo_periodic writes there (3D corner cells are
+ * not written).  sendbuf and recvbuf must differ. */
+int mhd_halo_exchange_self(mhd_ctx *ctx, void *fields, void *sendbuf, void *recvbuf,
+                           void *stream);
+
+/* mhd_rk3_substep restricted to the interior cells of `box`; every other
+ * cell of f_out, w and comp is left untouched.  Precondition: every cell
+ * within 3 of the box (halo included) holds current values.  Errors: as
+ * mhd_rk3_substep, and MHD_ERR_INVALID for a NULL or out-of-range box. */
+int mhd_rk3_substep_box(mhd_ctx *ctx, int32_t s, const mhd_box *box, const void *f_in,
+                        void *f_out, void *w, void *comp, double dt, void *stream);
+
+/* mhd_step with the segmented iteration.  Per substep: the boundary
+ * segments of the input are packed on `stream`; the exchange and unpack
+ * (as mhd_halo_exchange_self) run on `comm_stream` while the inner box is
+ * updated on `stream`; the six outer slabs follow on `stream` once the halo
+ * is in.  The inner box keeps 3 cells from the z faces, 32 from the x faces
+ * and 8 from the y faces (whole tiles of the fused kernels); on return all
+ * work of `comm_stream` is ordered before the rest of `stream`.  Results are
+ * identical to mhd_step's, bit for bit.  sendbuf, recvbuf: device buffers of
+ * mhd_halo_segment_elems elements.  Calls on one context must not overlap.
+ * Errors: as mhd_step, and MHD_ERR_INVALID for missing or equal buffers or a
+ * grid below 3 cells. */
+int mhd_step_segmented(mhd_ctx *ctx, void *const f[2], int32_t *cur, void *w, void *comp,
+                       double dt, int32_t nsteps, void *sendbuf, void *recvbuf, void *stream,
+                       void *comm_stream);
 
 /* Deterministic reduction `op` (enum mhd_reduce_op) over the interior of
  * field `field` of `fields`, accumulated in FP64 in a fixed order; the

@@ -10,15 +10,15 @@
 #include "mhd_internal.hpp"
 
 namespace mhd {
-hipError_t launch_rk3_direct(const Grid& g, const Phys& P, int precision, int s,
+hipError_t launch_rk3_direct(const Grid& g, const Phys& P, int precision, const Box& bx, int s,
                              const void* f_in, void* f_out, void* w, void* comp, double dt,
                              hipStream_t st);
-hipError_t launch_rk3_tiled(const Grid& g, const Phys& P, int precision, int s,
+hipError_t launch_rk3_tiled(const Grid& g, const Phys& P, int precision, const Box& bx, int s,
                             const void* f_in, void* f_out, void* w, void* comp, double dt,
-                            hipStream_t st, bool* launched);
-hipError_t launch_rk3_split(const Grid& g, const Phys& P, const Phys* P_dev, int precision,
-                            int s, const void* f_in, void* f_out, void* w, void* comp, double dt,
                             hipStream_t st);
+hipError_t launch_rk3_split(const Grid& g, const Phys& P, const Phys* P_dev, int precision,
+                            const Box& bx, int s, const void* f_in, void* f_out, void* w,
+                            void* comp, double dt, hipStream_t st);
 }  // namespace mhd
 
 using namespace mhd;
@@ -39,6 +39,9 @@ struct mhd_ctx {
     Grid grid;
     Phys phys;
     Phys* phys_dev;        // device copy of phys (read by the split kernel)
+    SegTable seg;          // packed halo segments of this grid
+    hipEvent_t ev_ready;   // segmented step: a substep's segments are packed
+    hipEvent_t ev_halo;    // segmented step: its halo has been unpacked
     int device;
     double* red_partials;  // device, REDUCE_BLOCKS doubles, then 1 result
     double* red_host;      // pinned host, 1 double
@@ -92,23 +95,80 @@ void drop_graph(StepGraph& gr)
     gr = StepGraph{};
 }
 
+int one_substep(mhd_ctx* ctx, int s, const Box& bx, const void* f_in, void* f_out, void* w,
+                void* comp, double dt, hipStream_t st)
+{
+    if (bx.x1 <= bx.x0 || bx.y1 <= bx.y0 || bx.z1 <= bx.z0) return MHD_OK;  // empty box
+    const Grid& g = ctx->grid;
+    const int prec = ctx->cfg.precision;
+    hipError_t e;
+    switch (ctx->cfg.kernel) {
+    case MHD_KERNEL_TILED:
+        e = launch_rk3_tiled(g, ctx->phys, prec, bx, s, f_in, f_out, w, comp, dt, st);
+        break;
+    case MHD_KERNEL_SPLIT:
+        e = launch_rk3_split(g, ctx->phys, ctx->phys_dev, prec, bx, s, f_in, f_out, w, comp, dt,
+                             st);
+        break;
+    default:
+        e = launch_rk3_direct(g, ctx->phys, prec, bx, s, f_in, f_out, w, comp, dt, st);
+        break;
+    }
+    return from_hip(e);
+}
+
 int one_substep(mhd_ctx* ctx, int s, const void* f_in, void* f_out, void* w, void* comp,
                 double dt, hipStream_t st)
 {
-    bool launched = false;
+    return one_substep(ctx, s, full_box(ctx->grid), f_in, f_out, w, comp, dt, st);
+}
+
+// The interior split of the segmented iteration (Section 3.3): the inner box,
+// which reads no halo, and the six slabs of the outer shell (z faces over the
+// whole plane, then y faces, then x faces), disjoint and together the whole
+// interior.  The shell is R planes thick at the z faces but a whole tile
+// (OUTER_X columns, OUTER_Y rows) at the x and y faces: the fused kernels
+// march in z over 32 x 8 tiles, and a slab thinner than a tile would leave
+// most of each tile's lanes idle.  Empty boxes are skipped by one_substep.
+constexpr int OUTER_X = 32, OUTER_Y = 8;
+void inner_outer(const Grid& g, Box& inner, Box outer[6])
+{
+    auto lo = [](int n, int w) { return n < w ? n : w; };
+    auto hi = [&](int n, int w) { return n - w > lo(n, w) ? n - w : lo(n, w); };
+    const int xa = lo(g.nx, OUTER_X), xb = hi(g.nx, OUTER_X), ya = lo(g.ny, OUTER_Y),
+              yb = hi(g.ny, OUTER_Y), za = lo(g.nz, R), zb = hi(g.nz, R);
+    inner = Box{xa, xb, ya, yb, za, zb};
+    outer[0] = Box{0, g.nx, 0, g.ny, 0, za};
+    outer[1] = Box{0, g.nx, 0, g.ny, zb, g.nz};
+    outer[2] = Box{0, g.nx, 0, ya, za, zb};
+    outer[3] = Box{0, g.nx, yb, g.ny, za, zb};
+    outer[4] = Box{0, xa, ya, yb, za, zb};
+    outer[5] = Box{xb, g.nx, ya, yb, za, zb};
+}
+
+// Exchange with the periodic neighbour (on one GPU: this subdomain itself, so
+// received segment k is sent segment NSEG-1-k, direction -d) and unpack, on
+// `st`; the segments must already be packed into sendbuf.
+int exchange_unpack(mhd_ctx* ctx, void* fields, void* sendbuf, void* recvbuf, hipStream_t st)
+{
+    const int es = (int)ctx->lay.elem_size;
     hipError_t e = hipSuccess;
-    if (ctx->cfg.kernel == MHD_KERNEL_TILED) {
-        e = launch_rk3_tiled(ctx->grid, ctx->phys, ctx->cfg.precision, s, f_in, f_out, w, comp, dt,
-                             st, &launched);
-    } else if (ctx->cfg.kernel == MHD_KERNEL_SPLIT) {
-        e = launch_rk3_split(ctx->grid, ctx->phys, ctx->phys_dev, ctx->cfg.precision, s, f_in,
-                             f_out, w, comp, dt, st);
-        launched = true;
+    for (int k = 0; k < NSEG && e == hipSuccess; ++k) {
+        const int src = NSEG - 1 - k;
+        e = hipMemcpyAsync((char*)recvbuf + ctx->seg.off[k] * es, (char*)sendbuf + ctx->seg.off[src] * es,
+                           (size_t)(ctx->seg.off[k + 1] - ctx->seg.off[k]) * es,
+                           hipMemcpyDeviceToDevice, st);
     }
-    if (e == hipSuccess && !launched)
-        e = launch_rk3_direct(ctx->grid, ctx->phys, ctx->cfg.precision, s, f_in, f_out, w, comp,
-                              dt, st);
+    if (e == hipSuccess) e = launch_segments(ctx->grid, ctx->seg, fields, recvbuf, es, true, st);
     return from_hip(e);
+}
+
+int halo_exchange(mhd_ctx* ctx, void* fields, void* sendbuf, void* recvbuf, hipStream_t st)
+{
+    const hipError_t e = launch_segments(ctx->grid, ctx->seg, fields, sendbuf,
+                                         (int)ctx->lay.elem_size, false, st);
+    if (e != hipSuccess) return from_hip(e);
+    return exchange_unpack(ctx, fields, sendbuf, recvbuf, st);
 }
 
 int substep_args_ok(mhd_ctx* ctx, int32_t s, const void* f_in, const void* f_out, const void* w,
@@ -269,6 +329,9 @@ int mhd_init(const mhd_config* cfg, mhd_ctx** out, mhd_layout* layout)
     P.cp_gm1 = cfg->cp * (cfg->gamma - 1.0);
 
     hipError_t e = hipMalloc(&ctx->red_partials, (REDUCE_BLOCKS + 1) * sizeof(double));
+    ctx->seg = seg_table(ctx->grid);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_ready, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_halo, hipEventDisableTiming);
     if (e == hipSuccess) e = hipMalloc(&ctx->phys_dev, sizeof(Phys));
     if (e == hipSuccess) e = hipMemcpy(ctx->phys_dev, &ctx->phys, sizeof(Phys), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipHostMalloc(&ctx->red_host, sizeof(double), hipHostMallocDefault);
@@ -292,6 +355,8 @@ void mhd_finalize(mhd_ctx* ctx)
     if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     if (ctx->red_partials) (void)hipFree(ctx->red_partials);
     if (ctx->phys_dev) (void)hipFree(ctx->phys_dev);
+    if (ctx->ev_ready) (void)hipEventDestroy(ctx->ev_ready);
+    if (ctx->ev_halo) (void)hipEventDestroy(ctx->ev_halo);
     if (ctx->red_host) (void)hipHostFree(ctx->red_host);
     delete ctx;
 }
@@ -330,6 +395,100 @@ int mhd_step(mhd_ctx* ctx, void* const f[2], int32_t* cur, void* w, void* comp, 
         }
         if (rc != MHD_OK) return rc;
         c ^= 1;  // three swaps per step
+        *cur = c;
+    }
+    return MHD_OK;
+}
+
+int mhd_rk3_substep_box(mhd_ctx* ctx, int32_t s, const mhd_box* box, const void* f_in,
+                        void* f_out, void* w, void* comp, double dt, void* stream)
+{
+    int rc = substep_args_ok(ctx, s, f_in, f_out, w, comp, dt);
+    if (rc != MHD_OK) return rc;
+    if (!box) return MHD_ERR_INVALID;
+    const Grid& g = ctx->grid;
+    if (box->x0 < 0 || box->y0 < 0 || box->z0 < 0 || box->x1 > g.nx || box->y1 > g.ny ||
+        box->z1 > g.nz || box->x0 > box->x1 || box->y0 > box->y1 || box->z0 > box->z1)
+        return MHD_ERR_INVALID;
+    if (ctx->cfg.precision != MHD_F32C) comp = nullptr;
+    const Box bx{box->x0, box->x1, box->y0, box->y1, box->z0, box->z1};
+    return one_substep(ctx, s, bx, f_in, f_out, w, comp, dt, (hipStream_t)stream);
+}
+
+int64_t mhd_halo_segment_elems(const mhd_ctx* ctx)
+{
+    if (!ctx) return -1;
+    return ctx->seg.off[NSEG];
+}
+
+namespace {
+bool exchange_ok(const mhd_ctx* ctx)
+{
+    return ctx->grid.nx >= R && ctx->grid.ny >= R && ctx->grid.nz >= R;
+}
+}  // namespace
+
+int mhd_halo_pack(mhd_ctx* ctx, const void* fields, void* sendbuf, void* stream)
+{
+    if (!ctx || !fields || !sendbuf || !exchange_ok(ctx)) return MHD_ERR_INVALID;
+    return from_hip(launch_segments(ctx->grid, ctx->seg, const_cast<void*>(fields), sendbuf,
+                                    (int)ctx->lay.elem_size, false, (hipStream_t)stream));
+}
+
+int mhd_halo_unpack(mhd_ctx* ctx, const void* recvbuf, void* fields, void* stream)
+{
+    if (!ctx || !fields || !recvbuf || !exchange_ok(ctx)) return MHD_ERR_INVALID;
+    return from_hip(launch_segments(ctx->grid, ctx->seg, fields, const_cast<void*>(recvbuf),
+                                    (int)ctx->lay.elem_size, true, (hipStream_t)stream));
+}
+
+int mhd_halo_exchange_self(mhd_ctx* ctx, void* fields, void* sendbuf, void* recvbuf,
+                           void* stream)
+{
+    if (!ctx || !fields || !sendbuf || !recvbuf || sendbuf == recvbuf || !exchange_ok(ctx))
+        return MHD_ERR_INVALID;
+    return halo_exchange(ctx, fields, sendbuf, recvbuf, (hipStream_t)stream);
+}
+
+int mhd_step_segmented(mhd_ctx* ctx, void* const f[2], int32_t* cur, void* w, void* comp,
+                       double dt, int32_t nsteps, void* sendbuf, void* recvbuf, void* stream,
+                       void* comm_stream)
+{
+    if (!ctx || !f || !cur || nsteps < 0 || (*cur != 0 && *cur != 1)) return MHD_ERR_INVALID;
+    int rc = substep_args_ok(ctx, 0, f[0], f[1], w, comp, dt);
+    if (rc != MHD_OK) return rc;
+    if (!sendbuf || !recvbuf || sendbuf == recvbuf || !exchange_ok(ctx)) return MHD_ERR_INVALID;
+    if (ctx->cfg.precision != MHD_F32C) comp = nullptr;
+    hipStream_t st = (hipStream_t)stream, cs = (hipStream_t)comm_stream;
+    Box inner, outer[6];
+    inner_outer(ctx->grid, inner, outer);
+    int c = *cur;
+    for (int32_t t = 0; t < nsteps; ++t) {
+        for (int s = 0; s < 3; ++s) {
+            // pack on the launch stream (so the exchange never waits behind
+            // the inner box); exchange and unpack on comm_stream while the
+            // inner box is updated; then the outer shell once the halo is in.
+            // (Outer slabs on comm_stream, concurrent with the inner box,
+            // measured no faster: the inner box's workgroups hold the CUs.)
+            hipError_t e = launch_segments(ctx->grid, ctx->seg, f[c], sendbuf,
+                                           (int)ctx->lay.elem_size, false, st);
+            if (e == hipSuccess) e = hipEventRecord(ctx->ev_ready, st);
+            if (e == hipSuccess) e = hipStreamWaitEvent(cs, ctx->ev_ready, 0);
+            if (e != hipSuccess) return from_hip(e);
+            rc = exchange_unpack(ctx, f[c], sendbuf, recvbuf, cs);
+            if (rc != MHD_OK) return rc;
+            e = hipEventRecord(ctx->ev_halo, cs);
+            if (e != hipSuccess) return from_hip(e);
+            rc = one_substep(ctx, s, inner, f[c], f[1 - c], w, comp, dt, st);
+            if (rc != MHD_OK) return rc;
+            e = hipStreamWaitEvent(st, ctx->ev_halo, 0);
+            if (e != hipSuccess) return from_hip(e);
+            for (const Box& b : outer) {
+                rc = one_substep(ctx, s, b, f[c], f[1 - c], w, comp, dt, st);
+                if (rc != MHD_OK) return rc;
+            }
+            c ^= 1;
+        }
         *cur = c;
     }
     return MHD_OK;

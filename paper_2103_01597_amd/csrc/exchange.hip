@@ -1,0 +1,134 @@
+// Packed halo segments for the segmented (inner / outer) iteration of
+// Section 3.3: the 6 side and 12 edge segments of a subdomain's 3-cell
+// boundary layer (corners are not read by the stencil, Section 5), packed
+// into one contiguous buffer, and the reverse scatter of received segments
+// into the halo.
+//
+// Segment d, a direction in {-1, 0, 1}^3 with one or two non-zero
+// components, covers per axis a:  d_a = -1: cells [0, 3),  0: [0, n_a),
+// +1: [n_a - 3, n_a)  of the interior (what the neighbour at offset d needs),
+// and its received counterpart fills the halo cells  d_a = -1: [-3, 0),
+// 0: [0, n_a), +1: [n_a, n_a + 3).  Within a segment the layout is
+// [field][z][y][x] over the segment's extents; segments follow each other in
+// the fixed order of seg_table.
+#include "mhd_internal.hpp"
+
+namespace mhd {
+
+SegTable seg_table(const Grid& g)
+{
+    SegTable t{};
+    int k = 0;
+    int64_t off = 0;
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int nnz = (dx != 0) + (dy != 0) + (dz != 0);
+                if (nnz == 0 || nnz == 3) continue;
+                const int d[3] = {dx, dy, dz}, n[3] = {g.nx, g.ny, g.nz};
+                int64_t cells = 1;
+                for (int a = 0; a < 3; ++a) {
+                    t.dir[k][a] = d[a];
+                    t.len[k][a] = d[a] == 0 ? n[a] : R;
+                    cells *= t.len[k][a];
+                }
+                t.off[k] = off;
+                off += NQ * cells;
+                ++k;
+            }
+    t.off[NSEG] = off;
+    return t;
+}
+
+namespace {
+
+constexpr int SEG_THREADS = 256;
+
+// Launch geometry: per segment its first workgroup, buffer offset, extents
+// and the interior start of its packed cells and of its halo cells.  The
+// kernel indexes it only with workgroup-uniform values, so it stays in
+// scalar registers.
+struct SegLaunch {
+    int blk[NSEG + 1];  // blk[NSEG]: workgroups per field
+    int64_t off[NSEG];
+    int len[NSEG][3];
+    int src[NSEG][3];
+    int dst[NSEG][3];
+};
+
+SegLaunch seg_launch(const Grid& g, const SegTable& t)
+{
+    SegLaunch L{};
+    const int n[3] = {g.nx, g.ny, g.nz};
+    int blocks = 0;
+    for (int k = 0; k < NSEG; ++k) {
+        L.blk[k] = blocks;
+        L.off[k] = t.off[k];
+        const int64_t per_field = (t.off[k + 1] - t.off[k]) / NQ;
+        blocks += (int)((per_field + SEG_THREADS - 1) / SEG_THREADS);
+        for (int a = 0; a < 3; ++a) {
+            const int d = t.dir[k][a];
+            L.len[k][a] = t.len[k][a];
+            L.src[k][a] = d == 0 ? 0 : d < 0 ? 0 : n[a] - R;
+            L.dst[k][a] = d == 0 ? 0 : d < 0 ? -R : n[a];
+        }
+    }
+    L.blk[NSEG] = blocks;
+    return L;
+}
+
+// One thread per packed element of one segment and field (blockIdx.y is the
+// field, so every index within a field fits 32 bits); UNPACK false: boundary
+// layer -> buffer, true: buffer -> halo.
+template <typename T, bool UNPACK>
+__global__ __launch_bounds__(SEG_THREADS) void k_segments(Grid g, SegLaunch L,
+                                                           T* __restrict__ grid_fields,
+                                                           T* __restrict__ buf)
+{
+    const int b = blockIdx.x;
+    int k = 0;
+#pragma unroll
+    for (int j = 1; j < NSEG; ++j) k += b >= L.blk[j];
+    const unsigned lx = L.len[k][0], ly = L.len[k][1], lz = L.len[k][2];
+    const unsigned e = (unsigned)(b - L.blk[k]) * SEG_THREADS + threadIdx.x;
+    const unsigned per_field = lx * ly * lz;
+    if (e >= per_field) return;
+    const int q = blockIdx.y;
+    const unsigned z = e / (lx * ly), r2 = e - z * (lx * ly);
+    const unsigned y = r2 / lx, x = r2 - y * lx;
+    const int cx = (UNPACK ? L.dst[k][0] : L.src[k][0]) + (int)x;
+    const int cy = (UNPACK ? L.dst[k][1] : L.src[k][1]) + (int)y;
+    const int cz = (UNPACK ? L.dst[k][2] : L.src[k][2]) + (int)z;
+    const int64_t c = (int64_t)q * g.fstride + g.interior + (int64_t)cz * g.mxy + (int64_t)cy * g.mx + cx;
+    const int64_t i = L.off[k] + (int64_t)q * per_field + e;
+    if (UNPACK)
+        grid_fields[c] = buf[i];
+    else
+        buf[i] = grid_fields[c];
+}
+
+template <typename T>
+void launch_typed(const Grid& g, const SegLaunch& L, T* fields, T* buf, bool unpack, hipStream_t st)
+{
+    const dim3 grid((unsigned)L.blk[NSEG], NQ), block(SEG_THREADS);
+    if (unpack)
+        hipLaunchKernelGGL((k_segments<T, true>), grid, block, 0, st, g, L, fields, buf);
+    else
+        hipLaunchKernelGGL((k_segments<T, false>), grid, block, 0, st, g, L, fields, buf);
+}
+
+}  // namespace
+
+hipError_t launch_segments(const Grid& g, const SegTable& t, void* fields, void* buf,
+                           int elem_size, bool unpack, hipStream_t st)
+{
+    const SegLaunch L = seg_launch(g, t);
+    if (L.blk[NSEG] == 0) return hipSuccess;
+    if (elem_size == 8)
+        launch_typed(g, L, (double*)fields, (double*)buf, unpack, st);
+    else
+        launch_typed(g, L, (float*)fields, (float*)buf, unpack, st);
+    return hipGetLastError();
+}
+
+}  // namespace mhd

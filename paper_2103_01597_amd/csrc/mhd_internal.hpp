@@ -22,6 +22,15 @@ struct Grid {
     int interior;     // (3*my + 3)*mx + 3
 };
 
+// A sub-box of the interior, half-open in interior cell indices:
+// x0 <= x < x1, y0 <= y < y1, z0 <= z < z1.  The fused kernels update the
+// cells of a box and leave every other cell untouched.
+struct Box {
+    int x0, x1, y0, y1, z0, z1;
+};
+
+__host__ __device__ inline Box full_box(const Grid& g) { return Box{0, g.nx, 0, g.ny, 0, g.nz}; }
+
 // Physics constants and grid spacings, in double; kernels convert.
 struct Phys {
     double inv_h[3];       // 1/h_i
@@ -179,11 +188,26 @@ __device__ __forceinline__ float kahan_add(float f, float y, float& c)
     return t;
 }
 
+// The 6 side and 12 edge segments of a subdomain's boundary layer (the
+// packed halo exchange of Section 3.3): per segment its direction d, its
+// extents (3 along every non-zero component of d, n_a otherwise) and its
+// element offset in a packed buffer of all 8 fields.  Segment NSEG-1-k has
+// direction -d of segment k.
+constexpr int NSEG = 18;
+struct SegTable {
+    int64_t off[NSEG + 1];  // off[NSEG]: total elements
+    int dir[NSEG][3];
+    int len[NSEG][3];
+};
+SegTable seg_table(const Grid& g);
+
 // ------------------------------------------------------------ launchers
 hipError_t launch_halo(const Grid& g, void* fields, int elem_size, hipStream_t st);
 
-hipError_t launch_rk3(const Grid& g, const Phys& P, int precision, int s, const void* f_in,
-                      void* f_out, void* w, void* comp, double dt, hipStream_t st);
+// Pack (unpack false: interior boundary layer -> buf) or unpack (buf -> halo).
+hipError_t launch_segments(const Grid& g, const SegTable& t, void* fields, void* buf,
+                           int elem_size, bool unpack, hipStream_t st);
+
 
 hipError_t launch_reduce(const Grid& g, const void* field, int elem_size, int op,
                          double* partials, int npartials, double* result, hipStream_t st);

@@ -14,7 +14,7 @@ namespace mhd {
 namespace {
 
 template <int PREC>
-__global__ __launch_bounds__(256) void k_rk3_direct(Grid g, Phys P, int s,
+__global__ __launch_bounds__(256) void k_rk3_direct(Grid g, Phys P, Box bx, int s,
                                                     const typename Prec<PREC>::T* __restrict__ fin,
                                                     typename Prec<PREC>::T* __restrict__ fout,
                                                     typename Prec<PREC>::T* __restrict__ w,
@@ -24,10 +24,10 @@ __global__ __launch_bounds__(256) void k_rk3_direct(Grid g, Phys P, int s,
     using T = typename Prec<PREC>::T;
     using Rt = typename Prec<PREC>::Rt;
     using D2 = typename Prec<PREC>::D2;
-    const int i = blockIdx.x * 64 + threadIdx.x;
-    const int j = blockIdx.y * 4 + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= g.nx || j >= g.ny)
+    const int i = bx.x0 + blockIdx.x * 64 + threadIdx.x;
+    const int j = bx.y0 + blockIdx.y * 4 + threadIdx.y;
+    const int k = bx.z0 + blockIdx.z;
+    if (i >= bx.x1 || j >= bx.y1)
         return;
     const int c = g.interior + k * g.mxy + j * g.mx + i;
     const int sx = 1, sy = g.mx, sz = g.mxy;
@@ -107,23 +107,23 @@ __global__ __launch_bounds__(256) void k_rk3_direct(Grid g, Phys P, int s,
 
 }  // namespace
 
-hipError_t launch_rk3_direct(const Grid& g, const Phys& P, int precision, int s,
+hipError_t launch_rk3_direct(const Grid& g, const Phys& P, int precision, const Box& bx, int s,
                              const void* f_in, void* f_out, void* w, void* comp, double dt,
                              hipStream_t st)
 {
     dim3 block(64, 4, 1);
-    dim3 grid((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz);
+    dim3 grid((bx.x1 - bx.x0 + 63) / 64, (bx.y1 - bx.y0 + 3) / 4, bx.z1 - bx.z0);
     switch (precision) {
     case MHD_F64:
-        hipLaunchKernelGGL(k_rk3_direct<MHD_F64>, grid, block, 0, st, g, P, s,
+        hipLaunchKernelGGL(k_rk3_direct<MHD_F64>, grid, block, 0, st, g, P, bx, s,
                            (const double*)f_in, (double*)f_out, (double*)w, (double*)comp, dt);
         break;
     case MHD_F32C:
-        hipLaunchKernelGGL(k_rk3_direct<MHD_F32C>, grid, block, 0, st, g, P, s,
+        hipLaunchKernelGGL(k_rk3_direct<MHD_F32C>, grid, block, 0, st, g, P, bx, s,
                            (const float*)f_in, (float*)f_out, (float*)w, (float*)comp, dt);
         break;
     default:
-        hipLaunchKernelGGL(k_rk3_direct<MHD_F32>, grid, block, 0, st, g, P, s,
+        hipLaunchKernelGGL(k_rk3_direct<MHD_F32>, grid, block, 0, st, g, P, bx, s,
                            (const float*)f_in, (float*)f_out, (float*)w, (float*)nullptr, dt);
         break;
     }

@@ -64,7 +64,8 @@ static_assert(NC % 64 == 0, "each group must be whole waves");
 
 struct TileMap {
     int ntx, nty;
-    int round;  // workgroups resident at once (0: plain order)
+    int nch, zc;  // z chunks per tile column, planes per chunk
+    int round;    // workgroups resident at once (0: plain order)
 };
 
 // Per-axis scale factors of the integer-weight stencils.
@@ -78,12 +79,36 @@ struct Scales {
 
 constexpr int NO_TILE = -1;
 
+// Z chunks: a launch lasts about (rounds of resident workgroups) x (planes
+// each workgroup marches, its 7 warm-up planes included).  A box with few
+// tile columns (a thin outer slab of the segmented iteration) or a tile count
+// just above a whole number of rounds marches in the z chunking of least
+// such cost, with chunks of at least ZCHUNK_MIN planes.
+constexpr int ZCHUNK_MIN = 16, WARM_PLANES = 7;
+inline void z_chunks(TileMap& m, int nzb)
+{
+    const int64_t cols = (int64_t)m.ntx * m.nty;
+    m.nch = 1;
+    m.zc = nzb;
+    if (cols <= 0 || m.round <= 0) return;
+    int64_t best = -1;
+    for (int want = 1; want == 1 || want <= nzb / ZCHUNK_MIN; ++want) {
+        const int zc = (nzb + want - 1) / want, nch = (nzb + zc - 1) / zc;
+        const int64_t cost = (nch * cols + m.round - 1) / m.round * (zc + WARM_PLANES);
+        if (best < 0 || cost < best) {
+            best = cost;
+            m.nch = nch;
+            m.zc = zc;
+        }
+    }
+}
+
 // Workgroup b -> tile, XCD-aware: within a round of `round` resident
 // workgroups, XCD k (which receives every 8th workgroup) gets a contiguous
 // run of tiles, so tiles sharing an L2 are spatial neighbours.
 __device__ __forceinline__ int tile_of_block(int b, const TileMap& m)
 {
-    const int tiles = m.ntx * m.nty;
+    const int tiles = m.ntx * m.nty * m.nch;
     if (m.round <= 0 || (m.round & 7) != 0) return b < tiles ? b : NO_TILE;
     const int r = b / m.round, w = b - r * m.round;
     const int rem = min(tiles - r * m.round, m.round);
@@ -100,8 +125,11 @@ __global__ __launch_bounds__(NTH, blocks_per_cu<PREC>()) void k_rk3_split(Grid g
                                                      typename Prec<PREC>::T* __restrict__ fout,
                                                      typename Prec<PREC>::T* __restrict__ w,
                                                      typename Prec<PREC>::T* __restrict__ comp,
-                                                     double dt)
+                                                     double dt, Box box)
 {
+    // the box's bounds as plain scalars (a struct captured by the lambdas
+    // below costs registers)
+    const int bx0 = box.x0, bx1 = box.x1, by0 = box.y0, by1 = box.y1;
     using T = typename Prec<PREC>::T;
     using Rt = typename Prec<PREC>::Rt;
     using D2 = typename Prec<PREC>::D2;
@@ -112,14 +140,17 @@ __global__ __launch_bounds__(NTH, blocks_per_cu<PREC>()) void k_rk3_split(Grid g
 
     const int tile = tile_of_block(blockIdx.x, map);
     if (tile == NO_TILE) return;  // the whole workgroup exits together
-    const int tx = tile % map.ntx, ty = tile / map.ntx;
-    const int x0 = tx * TX, y0 = ty * TY;
+    // tile = (chunk * nty + ty) * ntx + tx; the chunk marches its own z range
+    const int per_chunk = map.ntx * map.nty, ch = tile / per_chunk, txy = tile - ch * per_chunk;
+    const int tx = txy % map.ntx, ty = txy / map.ntx;
+    const int bz0 = box.z0 + ch * map.zc, bz1 = min(bz0 + map.zc, box.z1);
+    const int x0 = bx0 + tx * TX, y0 = by0 + ty * TY;
     // group index, made visibly wave-uniform so that the two groups' code
     // paths (each with its own registers and the same barriers) are scalar
     // branches
     const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x / NC);
     const int tid = threadIdx.x - grp * NC, lx = tid % TX, ly = tid / TX;
-    const bool active = (x0 + lx < g.nx) && (y0 + ly < g.ny);
+    const bool active = (x0 + lx < bx1) && (y0 + ly < by1);
     const bool extra = tid < EXTRA;
 
     auto field_ptr = [&](auto* base, int q) { return base + q * g.fstride; };
@@ -206,12 +237,15 @@ __global__ __launch_bounds__(NTH, blocks_per_cu<PREC>()) void k_rk3_split(Grid g
         auto cell_index = [&](int t) { return g.interior + t * g.mxy + (y0 + ly) * g.mx + (x0 + lx); };
 
         constexpr int SOFS = 8;
-        load_plane(-3);
-        for (int t = -7; t < g.nz; ++t) {
-            // warm-up planes (t < 0) run the whole computation too (branch-free
+        load_plane(bz0 - 3);
+        // u: plane index relative to the box start, so that the warm-up tests
+        // below compare against constants
+        for (int u = -7; u < bz1 - bz0; ++u) {
+            const int t = bz0 + u;
+            // warm-up planes (t < z0) run the whole computation too (branch-free
             // code schedules better); only their z state is kept
             const int s0 = (t + SOFS) & 3;
-            const bool live = t >= -3;  // uniform: plane t is in the ring
+            const bool live = u >= -3;  // uniform: plane t is in the ring
             Derivs<Rt> d;
             T fc[4], wnew[4], fnew[4], cnew[4];
             Rt S[3][3], divu = Rt(0), SS = Rt(0), B[3], J[3], jxB[3];
@@ -454,8 +488,8 @@ __global__ __launch_bounds__(NTH, blocks_per_cu<PREC>()) void k_rk3_split(Grid g
             // this plane's results go out: the vector-memory counter covers loads
             // and stores alike in issue order, so the next plane's waits for the
             // loads do not also wait for these stores
-            if (t + 5 <= g.nz + 2) load_plane(t + 5);
-            if (active && t + 1 >= 0 && t + 1 < g.nz) {
+            if (t + 5 <= bz1 + 2) load_plane(t + 5);
+            if (active && u + 1 >= 0 && t + 1 < bz1) {
                 const unsigned c = (unsigned)cell_index(t + 1);
                 if (s > 0) {
 #pragma unroll
@@ -466,7 +500,7 @@ __global__ __launch_bounds__(NTH, blocks_per_cu<PREC>()) void k_rk3_split(Grid g
                     for (int k4 = 0; k4 < 4; ++k4) cc[k4] = *at(field_ptr(comp, q0 + k4), c);
                 }
             }
-            if (t >= 0 && active) {
+            if (u >= 0 && active) {
                 const unsigned c = (unsigned)cell_index(t);
 #pragma unroll
                 for (int k4 = 0; k4 < 4; ++k4) {
@@ -484,8 +518,8 @@ __global__ __launch_bounds__(NTH, blocks_per_cu<PREC>()) void k_rk3_split(Grid g
 }
 
 template <int PREC>
-hipError_t launch_one(const Grid& g, const Phys& P, const Phys* P_dev, int s, const void* f_in,
-                      void* f_out, void* w, void* comp, double dt, hipStream_t st)
+hipError_t launch_one(const Grid& g, const Phys& P, const Phys* P_dev, const Box& bx, int s,
+                      const void* f_in, void* f_out, void* w, void* comp, double dt, hipStream_t st)
 {
     using T = typename Prec<PREC>::T;
     static int round = -1;  // resident workgroups per round on this device
@@ -504,9 +538,10 @@ hipError_t launch_one(const Grid& g, const Phys& P, const Phys* P_dev, int s, co
         round = per_cu * cus;
     }
     TileMap m;
-    m.ntx = (g.nx + TX - 1) / TX;
-    m.nty = (g.ny + TY - 1) / TY;
+    m.ntx = (bx.x1 - bx.x0 + TX - 1) / TX;
+    m.nty = (bx.y1 - bx.y0 + TY - 1) / TY;
     m.round = round;
+    z_chunks(m, bx.z1 - bx.z0);
     Scales sc;
     for (int a = 0; a < 3; ++a) {
         sc.d1[a] = P.inv_h[a] / 60.0;
@@ -518,10 +553,10 @@ hipError_t launch_one(const Grid& g, const Phys& P, const Phys* P_dev, int s, co
         sc.wxz[k] = wm[k] * P.inv_h[0] * P.inv_h[2] / 720.0;
         sc.wyz[k] = wm[k] * P.inv_h[1] * P.inv_h[2] / 720.0;
     }
-    const int tiles = m.ntx * m.nty;
+    const int tiles = m.ntx * m.nty * m.nch;
     const int blocks = (round > 0 && (round & 7) == 0) ? (tiles + round - 1) / round * round : tiles;
     hipLaunchKernelGGL(k_rk3_split<PREC>, dim3(blocks), dim3(NTH), lds, st, g, P_dev, sc, m, s,
-                       (const T*)f_in, (T*)f_out, (T*)w, (T*)comp, dt);
+                       (const T*)f_in, (T*)f_out, (T*)w, (T*)comp, dt, bx);
     return hipGetLastError();
 }
 
@@ -529,14 +564,14 @@ hipError_t launch_one(const Grid& g, const Phys& P, const Phys* P_dev, int s, co
 
 // P (host copy) sets the stencil scales; P_dev (device copy of the same
 // values) is what the kernel's physics reads.
-hipError_t launch_rk3_split(const Grid& g, const Phys& P, const Phys* P_dev, int precision, int s,
-                            const void* f_in, void* f_out, void* w, void* comp, double dt,
-                            hipStream_t st)
+hipError_t launch_rk3_split(const Grid& g, const Phys& P, const Phys* P_dev, int precision,
+                            const Box& bx, int s, const void* f_in, void* f_out, void* w,
+                            void* comp, double dt, hipStream_t st)
 {
     switch (precision) {
-    case MHD_F64: return launch_one<MHD_F64>(g, P, P_dev, s, f_in, f_out, w, nullptr, dt, st);
-    case MHD_F32C: return launch_one<MHD_F32C>(g, P, P_dev, s, f_in, f_out, w, comp, dt, st);
-    default: return launch_one<MHD_F32>(g, P, P_dev, s, f_in, f_out, w, nullptr, dt, st);
+    case MHD_F64: return launch_one<MHD_F64>(g, P, P_dev, bx, s, f_in, f_out, w, nullptr, dt, st);
+    case MHD_F32C: return launch_one<MHD_F32C>(g, P, P_dev, bx, s, f_in, f_out, w, comp, dt, st);
+    default: return launch_one<MHD_F32>(g, P, P_dev, bx, s, f_in, f_out, w, nullptr, dt, st);
     }
 }
 

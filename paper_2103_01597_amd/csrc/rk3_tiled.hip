@@ -62,6 +62,7 @@ constexpr size_t lds_bytes() { return sizeof(T) * NSLOT * SLOT; }
 
 struct TileMap {
     int ntx, nty;   // tiles per axis
+    int nch, zc;    // z chunks per tile column, planes per chunk
     int round;      // workgroups resident at once (0: plain order)
 };
 
@@ -76,6 +77,30 @@ struct Scales {
 
 constexpr int NO_TILE = -1;
 
+// Z chunks: a launch lasts about (rounds of resident workgroups) x (planes
+// each workgroup marches, its 7 warm-up planes included).  A box with few
+// tile columns (a thin outer slab of the segmented iteration) or a tile count
+// just above a whole number of rounds marches in the z chunking of least
+// such cost, with chunks of at least ZCHUNK_MIN planes.
+constexpr int ZCHUNK_MIN = 16, WARM_PLANES = 7;
+inline void z_chunks(TileMap& m, int nzb)
+{
+    const int64_t cols = (int64_t)m.ntx * m.nty;
+    m.nch = 1;
+    m.zc = nzb;
+    if (cols <= 0 || m.round <= 0) return;
+    int64_t best = -1;
+    for (int want = 1; want == 1 || want <= nzb / ZCHUNK_MIN; ++want) {
+        const int zc = (nzb + want - 1) / want, nch = (nzb + zc - 1) / zc;
+        const int64_t cost = (nch * cols + m.round - 1) / m.round * (zc + WARM_PLANES);
+        if (best < 0 || cost < best) {
+            best = cost;
+            m.nch = nch;
+            m.zc = zc;
+        }
+    }
+}
+
 // Workgroup b -> tile.  Hardware hands consecutive workgroups to the 8 XCDs
 // in turn; within one round of `round` resident workgroups, XCD k gets the
 // k-th contiguous run of tiles (row-major tile order), so the tiles that run
@@ -83,7 +108,7 @@ constexpr int NO_TILE = -1;
 // covers a compact band of tile rows.
 __device__ __forceinline__ int tile_of_block(int b, const TileMap& m)
 {
-    const int tiles = m.ntx * m.nty;
+    const int tiles = m.ntx * m.nty * m.nch;
     if (m.round <= 0 || (m.round & 7) != 0) return b < tiles ? b : NO_TILE;
     const int r = b / m.round, w = b - r * m.round;
     const int rem = min(tiles - r * m.round, m.round);  // tiles in this round
@@ -108,8 +133,11 @@ __global__ __launch_bounds__(NT, blocks_per_cu<PREC>()) void k_rk3_tiled(Grid g,
                                                      typename Prec<PREC>::T* __restrict__ fout,
                                                      typename Prec<PREC>::T* __restrict__ w,
                                                      typename Prec<PREC>::T* __restrict__ comp,
-                                                     double dt)
+                                                     double dt, Box box)
 {
+    // the box's bounds as plain scalars (a struct captured by the lambdas
+    // below costs registers)
+    const int bx0 = box.x0, bx1 = box.x1, by0 = box.y0, by1 = box.y1;
     using T = typename Prec<PREC>::T;
     using Rt = typename Prec<PREC>::Rt;
     using D2 = typename Prec<PREC>::D2;
@@ -118,10 +146,13 @@ __global__ __launch_bounds__(NT, blocks_per_cu<PREC>()) void k_rk3_tiled(Grid g,
 
     const int tile = tile_of_block(blockIdx.x, map);
     if (tile == NO_TILE) return;  // the whole workgroup exits together
-    const int tx = tile % map.ntx, ty = tile / map.ntx;
-    const int x0 = tx * TX, y0 = ty * TY;
+    // tile = (chunk * nty + ty) * ntx + tx; the chunk marches its own z range
+    const int per_chunk = map.ntx * map.nty, ch = tile / per_chunk, txy = tile - ch * per_chunk;
+    const int tx = txy % map.ntx, ty = txy / map.ntx;
+    const int bz0 = box.z0 + ch * map.zc, bz1 = min(bz0 + map.zc, box.z1);
+    const int x0 = bx0 + tx * TX, y0 = by0 + ty * TY;
     const int tid = threadIdx.x, lx = tid % TX, ly = tid / TX;
-    const bool active = (x0 + lx < g.nx) && (y0 + ly < g.ny);
+    const bool active = (x0 + lx < bx1) && (y0 + ly < by1);
     const bool extra = tid < EXTRA;
 
     // Global addressing: a uniform field base plus a 32-bit byte offset (every
@@ -206,13 +237,16 @@ __global__ __launch_bounds__(NT, blocks_per_cu<PREC>()) void k_rk3_tiled(Grid g,
     auto cell_index = [&](int t) { return g.interior + t * g.mxy + (y0 + ly) * g.mx + (x0 + lx); };
 
     constexpr int SOFS = 8;  // keeps (t + SOFS) non-negative for slot arithmetic
-    load_plane(-3);
-    for (int t = -7; t < g.nz; ++t) {
-        if (t >= -3) {
+    load_plane(bz0 - 3);
+    // u: plane index relative to the box start, so that the warm-up tests
+    // below compare against constants
+    for (int u = -7; u < bz1 - bz0; ++u) {
+        const int t = bz0 + u;
+        if (u >= -3) {
             const int s0 = (t + SOFS) & 3, s1 = (t + 1 + SOFS) & 3, s2 = (t + 2 + SOFS) & 3,
                       s3 = (t + 3 + SOFS) & 3;
             const int sl[4] = {s0, s1, s2, s3};
-            // warm-up planes (t < 0) run the whole computation too (branch-free
+            // warm-up planes (t < z0) run the whole computation too (branch-free
             // code schedules better); only their z state is kept
 
             Derivs<Rt> d;
@@ -412,8 +446,8 @@ __global__ __launch_bounds__(NT, blocks_per_cu<PREC>()) void k_rk3_tiled(Grid g,
         // plane's waits for them do not also wait for these stores.
         __syncthreads();  // every read of plane t is done
         store_plane((t + 4 + SOFS) & 3);
-        if (t + 5 <= g.nz + 2) load_plane(t + 5);
-        if (active && t + 1 >= 0 && t + 1 < g.nz) {
+        if (t + 5 <= bz1 + 2) load_plane(t + 5);
+        if (active && u + 1 >= 0 && t + 1 < bz1) {
             const unsigned c = (unsigned)cell_index(t + 1);
             if (s > 0) {
 #pragma unroll
@@ -424,7 +458,7 @@ __global__ __launch_bounds__(NT, blocks_per_cu<PREC>()) void k_rk3_tiled(Grid g,
                 for (int q = 0; q < NQ; ++q) cc[q] = *at(field_ptr(comp, q), c);
             }
         }
-        if (t >= 0 && active) {
+        if (u >= 0 && active) {
             const unsigned c = (unsigned)cell_index(t);
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
@@ -438,8 +472,8 @@ __global__ __launch_bounds__(NT, blocks_per_cu<PREC>()) void k_rk3_tiled(Grid g,
 }
 
 template <int PREC>
-hipError_t launch_one(const Grid& g, const Phys& P, int s, const void* f_in, void* f_out, void* w,
-                      void* comp, double dt, hipStream_t st)
+hipError_t launch_one(const Grid& g, const Phys& P, const Box& bx, int s, const void* f_in,
+                      void* f_out, void* w, void* comp, double dt, hipStream_t st)
 {
     using T = typename Prec<PREC>::T;
     static int round = -1;  // resident workgroups per round on this device
@@ -458,9 +492,10 @@ hipError_t launch_one(const Grid& g, const Phys& P, int s, const void* f_in, voi
         round = per_cu * cus;
     }
     TileMap m;
-    m.ntx = (g.nx + TX - 1) / TX;
-    m.nty = (g.ny + TY - 1) / TY;
+    m.ntx = (bx.x1 - bx.x0 + TX - 1) / TX;
+    m.nty = (bx.y1 - bx.y0 + TY - 1) / TY;
     m.round = round;
+    z_chunks(m, bx.z1 - bx.z0);
     Scales sc;
     for (int a = 0; a < 3; ++a) {
         sc.d1[a] = P.inv_h[a] / 60.0;
@@ -472,26 +507,25 @@ hipError_t launch_one(const Grid& g, const Phys& P, int s, const void* f_in, voi
         sc.wxz[m3] = wm[m3] * P.inv_h[0] * P.inv_h[2] / 720.0;
         sc.wyz[m3] = wm[m3] * P.inv_h[1] * P.inv_h[2] / 720.0;
     }
-    const int tiles = m.ntx * m.nty;
+    const int tiles = m.ntx * m.nty * m.nch;
     // with the XCD mapping the last round may name tiles past the end; those
     // workgroups exit at once
     const int blocks = (round > 0 && (round & 7) == 0) ? (tiles + round - 1) / round * round : tiles;
     hipLaunchKernelGGL(k_rk3_tiled<PREC>, dim3(blocks), dim3(NT), lds, st, g, P, sc, m, s,
-                       (const T*)f_in, (T*)f_out, (T*)w, (T*)comp, dt);
+                       (const T*)f_in, (T*)f_out, (T*)w, (T*)comp, dt, bx);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_rk3_tiled(const Grid& g, const Phys& P, int precision, int s, const void* f_in,
-                            void* f_out, void* w, void* comp, double dt, hipStream_t st,
-                            bool* launched)
+hipError_t launch_rk3_tiled(const Grid& g, const Phys& P, int precision, const Box& bx, int s,
+                            const void* f_in, void* f_out, void* w, void* comp, double dt,
+                            hipStream_t st)
 {
-    *launched = true;
     switch (precision) {
-    case MHD_F64: return launch_one<MHD_F64>(g, P, s, f_in, f_out, w, nullptr, dt, st);
-    case MHD_F32C: return launch_one<MHD_F32C>(g, P, s, f_in, f_out, w, comp, dt, st);
-    default: return launch_one<MHD_F32>(g, P, s, f_in, f_out, w, nullptr, dt, st);
+    case MHD_F64: return launch_one<MHD_F64>(g, P, bx, s, f_in, f_out, w, nullptr, dt, st);
+    case MHD_F32C: return launch_one<MHD_F32C>(g, P, bx, s, f_in, f_out, w, comp, dt, st);
+    default: return launch_one<MHD_F32>(g, P, bx, s, f_in, f_out, w, nullptr, dt, st);
     }
 }
 

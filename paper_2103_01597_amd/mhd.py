@@ -26,7 +26,9 @@ STATUS = {0: "MHD_OK", 1: "MHD_ERR_INVALID", 2: "MHD_ERR_NO_DEVICE", 3: "MHD_ERR
 
 # every symbol declared in include/mhd.h
 EXPORTS = ("mhd_config_default", "mhd_init", "mhd_finalize", "mhd_strerror",
-           "mhd_halo_periodic", "mhd_rk3_substep", "mhd_step", "mhd_reduce")
+           "mhd_halo_periodic", "mhd_rk3_substep", "mhd_step", "mhd_halo_segment_elems",
+           "mhd_halo_pack", "mhd_halo_unpack", "mhd_halo_exchange_self", "mhd_rk3_substep_box",
+           "mhd_step_segmented", "mhd_reduce")
 
 
 class Config(ctypes.Structure):
@@ -43,6 +45,10 @@ class Config(ctypes.Structure):
 class Layout(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("mx", "my", "mz", "field_stride", "elem_size", "interior_offset", "total_elems")]
+
+
+class Box(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("x0", "x1", "y0", "y1", "z0", "z1")]
 
 
 class MhdError(RuntimeError):
@@ -74,7 +80,17 @@ def lib():
     L.mhd_rk3_substep.argtypes = [vp, i32, vp, vp, vp, vp, dbl, vp]
     L.mhd_step.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(i32), vp, vp, dbl, i32, vp]
     L.mhd_reduce.argtypes = [vp, vp, i32, i32, ctypes.POINTER(dbl), vp]
-    for fn in ("mhd_init", "mhd_halo_periodic", "mhd_rk3_substep", "mhd_step", "mhd_reduce"):
+    L.mhd_halo_segment_elems.argtypes = [vp]
+    L.mhd_halo_segment_elems.restype = ctypes.c_int64
+    L.mhd_halo_pack.argtypes = [vp, vp, vp, vp]
+    L.mhd_halo_unpack.argtypes = [vp, vp, vp, vp]
+    L.mhd_halo_exchange_self.argtypes = [vp, vp, vp, vp, vp]
+    L.mhd_rk3_substep_box.argtypes = [vp, i32, ctypes.POINTER(Box), vp, vp, vp, vp, dbl, vp]
+    L.mhd_step_segmented.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(i32), vp, vp, dbl,
+                                     i32, vp, vp, vp, vp]
+    for fn in ("mhd_init", "mhd_halo_periodic", "mhd_rk3_substep", "mhd_step", "mhd_reduce",
+               "mhd_halo_pack", "mhd_halo_unpack", "mhd_halo_exchange_self",
+               "mhd_rk3_substep_box", "mhd_step_segmented"):
         getattr(L, fn).restype = ctypes.c_int
     _lib = L
     return L
@@ -197,6 +213,48 @@ class Solver:
         c = ctypes.c_int32(cur)
         _check("mhd_step", lib().mhd_step(self._ctx, arr, ctypes.byref(c), _ptr(w), _ptr(comp),
                                           dt, nsteps, _stream(stream)))
+        return c.value
+
+    # ---------------------------------------------- segmented iteration
+    def halo_segment_elems(self) -> int:
+        return int(lib().mhd_halo_segment_elems(self._ctx))
+
+    def segment_buffer(self):
+        import torch
+        return torch.empty(self.halo_segment_elems(), dtype=self.torch_dtype, device="cuda")
+
+    def halo_pack(self, fields, sendbuf, stream=None):
+        _check("mhd_halo_pack", lib().mhd_halo_pack(self._ctx, _ptr(fields), _ptr(sendbuf),
+                                                    _stream(stream)))
+
+    def halo_unpack(self, recvbuf, fields, stream=None):
+        _check("mhd_halo_unpack", lib().mhd_halo_unpack(self._ctx, _ptr(recvbuf), _ptr(fields),
+                                                        _stream(stream)))
+
+    def halo_exchange_self(self, fields, sendbuf, recvbuf, stream=None):
+        _check("mhd_halo_exchange_self",
+               lib().mhd_halo_exchange_self(self._ctx, _ptr(fields), _ptr(sendbuf), _ptr(recvbuf),
+                                            _stream(stream)))
+
+    def rk3_substep_box(self, s, box, f_in, f_out, w, comp=None, dt=1e-3, stream=None):
+        """box: (x0, x1, y0, y1, z0, z1) in interior cell indices, half-open."""
+        b = Box(*[int(v) for v in box])
+        _check("mhd_rk3_substep_box",
+               lib().mhd_rk3_substep_box(self._ctx, s, ctypes.byref(b), _ptr(f_in), _ptr(f_out),
+                                         _ptr(w), _ptr(comp), dt, _stream(stream)))
+
+    def step_segmented(self, f, cur, w, comp=None, dt=1e-3, nsteps=1, sendbuf=None,
+                       recvbuf=None, stream=None, comm_stream=None) -> int:
+        """mhd_step with the inner/outer split and the packed halo exchange on
+        comm_stream; returns the result's index."""
+        arr = (ctypes.c_void_p * 2)(f[0].data_ptr(), f[1].data_ptr())
+        c = ctypes.c_int32(cur)
+        sendbuf = self.segment_buffer() if sendbuf is None else sendbuf
+        recvbuf = self.segment_buffer() if recvbuf is None else recvbuf
+        _check("mhd_step_segmented",
+               lib().mhd_step_segmented(self._ctx, arr, ctypes.byref(c), _ptr(w), _ptr(comp), dt,
+                                        nsteps, _ptr(sendbuf), _ptr(recvbuf), _stream(stream),
+                                        _stream(comm_stream)))
         return c.value
 
     def reduce(self, buf, field, op, stream=None) -> float:

@@ -55,6 +55,12 @@ def test_strerror_and_defaults(L):
     assert cfg.kernel == 2  # MHD_KERNEL_SPLIT for FP64
 
 
+def test_segment_count_of_null_context(L):
+    L.mhd_halo_segment_elems.restype = ctypes.c_int64
+    L.mhd_halo_segment_elems.argtypes = [ctypes.c_void_p]
+    assert L.mhd_halo_segment_elems(None) == -1
+
+
 def _init(L, **kw):
     cfg = mhd.Config()
     L.mhd_config_default(ctypes.byref(cfg), 8, 8, 8, 0)

@@ -124,8 +124,10 @@ def test_full_step_oracle32(mhd, kernel):
     assert max(e) <= TOL_F64
 
 
+# (20, 12, 70) and (40, 16, 100) have few tile columns and a tall z extent:
+# the fused kernels march them in z chunks (the last one ragged)
 @pytest.mark.parametrize("shape", [(48, 40, 32), (37, 29, 31), (5, 7, 6), (64, 3, 2), (1, 1, 1),
-                                   (130, 9, 12), (33, 17, 3)])
+                                   (130, 9, 12), (33, 17, 3), (20, 12, 70), (40, 16, 100)])
 @pytest.mark.parametrize("kernel", KERNELS)
 def test_full_step_ragged_sizes(mhd, shape, kernel):
     say(f"full step {shape} {kernel}")

@@ -34,7 +34,8 @@ _lib = None
 
 NQ = 8
 FIELD_NAMES = ("lnrho", "ux", "uy", "uz", "ss", "ax", "ay", "az")
-R = 3  # stencil radius (Section 2, Eq. 1; sixth order: k = 2r)
+R = 3  # default stencil radius (Section 2, Eq. 1; sixth order: k = 2r)
+ORDERS = (2, 4, 6, 8)  # the stencil orders of Section 4 (radius r = order / 2)
 
 OPS = {"d1x": 0, "d1y": 1, "d1z": 2, "d2x": 3, "d2y": 4, "d2z": 5,
        "dxy": 6, "dxz": 7, "dyz": 8}
@@ -42,7 +43,7 @@ OPS = {"d1x": 0, "d1y": 1, "d1z": 2, "d2x": 3, "d2y": 4, "d2z": 5,
 
 class _Params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
-                ("pad_", ctypes.c_int32),
+                ("radius", ctypes.c_int32),
                 ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double),
                 ("cs0", ctypes.c_double), ("gamma", ctypes.c_double), ("cp", ctypes.c_double),
                 ("lnrho0", ctypes.c_double), ("mu0", ctypes.c_double), ("nu", ctypes.c_double),
@@ -69,9 +70,11 @@ class Params:
     eta: float = 5e-3
     K: float = 5e-3
     bext: tuple = field(default=(0.0, 0.0, 0.0))
+    order: int = 6  # stencil order k = 2r (Section 4)
 
     def _c(self) -> _Params:
         p = _Params()
+        p.radius = _radius(self.order)
         for name in ("nx", "ny", "nz", "lx", "ly", "lz", "cs0", "gamma", "cp", "lnrho0",
                      "mu0", "nu", "zeta", "eta", "K"):
             setattr(p, name, getattr(self, name))
@@ -89,8 +92,9 @@ def _load():
     lib = ctypes.CDLL(_LIB_PATH)
     dp = ctypes.POINTER(ctypes.c_double)
     pp = ctypes.POINTER(_Params)
-    lib.oracle_deriv.argtypes = [ctypes.c_int32] * 3 + [ctypes.c_double] * 3 + [dp, ctypes.c_int32, dp]
-    lib.oracle_weights.argtypes = [dp, dp]
+    lib.oracle_deriv.argtypes = ([ctypes.c_int32] * 3 + [ctypes.c_double] * 3 +
+                                 [ctypes.c_int32, dp, ctypes.c_int32, dp])
+    lib.oracle_weights.argtypes = [ctypes.c_int32, dp, dp]
     lib.oracle_rk3_coeffs.argtypes = [dp, dp]
     lib.oracle_rhs.argtypes = [pp, dp, dp]
     lib.oracle_rk3_update.argtypes = [ctypes.c_int64, ctypes.c_int32, dp, dp, dp, ctypes.c_double]
@@ -98,7 +102,7 @@ def _load():
     lib.oracle_step.argtypes = [pp, dp, dp, ctypes.c_double, ctypes.c_int32]
     lib.oracle_substep_at.argtypes = [pp, ctypes.c_int32, dp, dp, ctypes.c_double, ctypes.c_int64,
                                       ctypes.POINTER(ctypes.c_int64), dp, dp]
-    for fn in ("oracle_deriv", "oracle_rhs", "oracle_rk3_update", "oracle_substep", "oracle_step",
+    for fn in ("oracle_deriv", "oracle_weights", "oracle_rhs", "oracle_rk3_update", "oracle_substep", "oracle_step",
                "oracle_substep_at"):
         getattr(lib, fn).restype = ctypes.c_int
     _lib = lib
@@ -117,11 +121,19 @@ def _fields(f: np.ndarray, p: Params) -> np.ndarray:
     return f
 
 
-def weights():
-    """(a1, a2): the first/second-derivative weights for offsets -3..3."""
-    a1 = np.zeros(7)
-    a2 = np.zeros(7)
-    _load().oracle_weights(_ptr(a1), _ptr(a2))
+def _radius(order: int) -> int:
+    if order not in ORDERS:
+        raise ValueError(f"stencil order must be one of {ORDERS}, got {order}")
+    return order // 2
+
+
+def weights(order: int = 6):
+    """(a1, a2): the first/second-derivative weights for offsets -r..r."""
+    r = _radius(order)
+    a1 = np.zeros(2 * r + 1)
+    a2 = np.zeros(2 * r + 1)
+    if _load().oracle_weights(r, _ptr(a1), _ptr(a2)) != 0:
+        raise ValueError("oracle_weights failed")
     return a1, a2
 
 
@@ -132,12 +144,14 @@ def rk3_coeffs():
     return a, b
 
 
-def deriv(f: np.ndarray, op: str, lengths=(2 * math.pi,) * 3) -> np.ndarray:
-    """One derivative operator on one periodic field of shape (nz, ny, nx)."""
+def deriv(f: np.ndarray, op: str, lengths=(2 * math.pi,) * 3, order: int = 6) -> np.ndarray:
+    """One derivative operator of the given stencil order on one periodic
+    field of shape (nz, ny, nx)."""
     f = np.ascontiguousarray(f, dtype=np.float64)
     nz, ny, nx = f.shape
     out = np.empty_like(f)
-    rc = _load().oracle_deriv(nx, ny, nz, *[float(x) for x in lengths], _ptr(f), OPS[op], _ptr(out))
+    rc = _load().oracle_deriv(nx, ny, nz, *[float(x) for x in lengths], _radius(order), _ptr(f),
+                              OPS[op], _ptr(out))
     if rc != 0:
         raise ValueError("oracle_deriv failed")
     return out

@@ -9,22 +9,25 @@
  * What it follows (Pekkila et al., "Scalable communication for high-order
  * stencil computations using CUDA-aware MPI"):
  *   - Section 2: a grid of n cells per axis; the stencil radius r is the
- *     largest Chebyshev distance of a stencil point (Eq. 1).  Here r = 3.
+ *     largest Chebyshev distance of a stencil point (Eq. 1).  Section 4
+ *     lists 2nd-, 4th-, 6th- and 8th-order stencils (k = 2r, r = 1..4);
+ *     r is a parameter here, 3 by default.
  *   - Section 3.3: on a periodic domain a halo index s maps to the interior
  *     index ((s - r) mod n) + r.  The oracle keeps no halo at all; it reads
  *     the neighbour at offset m of interior cell i as cell (i + m) mod n,
  *     which is the same value the halo holds.
- *   - Section 4, Eq. (stencil-fd): sixth-order (k = 2r) central differences
- *     whose stencil holds only points z(x +- y) with x, y standard basis
- *     vectors or 0 -- the three axis lines and the planar diagonals.  Hence
- *     mixed derivatives use the diagonal points only (see d_mixed below).
+ *   - Section 4, Eq. (stencil-fd): order-2r central differences whose
+ *     stencil holds only points z(x +- y), |z| <= r, with x, y standard
+ *     basis vectors or 0 -- the three axis lines and the planar diagonals.
+ *     Hence mixed derivatives use the diagonal points only (see d_mixed).
  *   - Section 4: time integration by Williamson's third-order low-storage
  *     (2N) Runge-Kutta scheme.
  *   - Appendix B, Eqs. B.1-B.4 and Tables B.1-B.2: the non-ideal MHD system
  *     for ln(rho), u, s and A, in non-conservative form.
  *
  * Readings where the paper is silent (each listed in the design notes):
- *   - derivative weights: the standard sixth-order central weights;
+ *   - derivative weights: the standard central weights of order 2r (the
+ *     unique ones exact on polynomials of degree 2r on the 2r+1 points);
  *   - mixed derivative: difference of the second derivatives along the
  *     two diagonals of the plane, each with the pure second-derivative
  *     weights, divided by 4 h_a h_b;
@@ -35,7 +38,7 @@
  *     Ds/Dt = (K/rho)(lap lnT + |grad lnT|^2)
  *             + (1/T)(eta mu0 j.j / rho + 2 nu S:S + zeta (div u)^2);
  *   - j = (grad(div A) - lap A)/mu0, built from second derivatives (the
- *     radius-3 form of mu0^-1 curl curl A);
+ *     radius-r form of mu0^-1 curl curl A);
  *   - B = curl A + B_ext with an optional uniform B_ext (zero by default);
  *   - S_ij = (d_j u_i + d_i u_j)/2 - delta_ij div(u)/3.
  *
@@ -53,20 +56,32 @@
 enum { Q_LNRHO = 0, Q_UX, Q_UY, Q_UZ, Q_SS, Q_AX, Q_AY, Q_AZ };
 
 typedef struct {
-    int32_t nx, ny, nz, pad_;
+    int32_t nx, ny, nz, radius; /* radius r = 1..4: order 2r */
     double lx, ly, lz;
     double cs0, gamma, cp, lnrho0, mu0, nu, zeta, eta, K;
     double bext[3];
 } oracle_params;
 
-/* Sixth-order central weights for offsets m = -3..3.
- * First derivative:  f'(0)  ~ (1/h)   * sum_m A1[m+3] f(m)
- * Second derivative: f''(0) ~ (1/h^2) * sum_m A2[m+3] f(m)            */
-static const double A1[7] = {
-    -1.0 / 60.0, 9.0 / 60.0, -45.0 / 60.0, 0.0, 45.0 / 60.0, -9.0 / 60.0, 1.0 / 60.0};
-static const double A2[7] = {
-    2.0 / 180.0, -27.0 / 180.0, 270.0 / 180.0, -490.0 / 180.0,
-    270.0 / 180.0, -27.0 / 180.0, 2.0 / 180.0};
+#define RMAX 4
+
+/* Central weights of order 2r for offsets m = -r..r, stored at [r-1][m+4]
+ * (zero outside |m| <= r), written as integer numerators over one
+ * denominator per row:
+ *   first derivative:  f'(0)  ~ (1/h)   * sum_m A1[r-1][m+4] f(m)
+ *   second derivative: f''(0) ~ (1/h^2) * sum_m A2[r-1][m+4] f(m)       */
+static const double A1[RMAX][2 * RMAX + 1] = {
+    {0, 0, 0, -1.0 / 2.0, 0.0, 1.0 / 2.0, 0, 0, 0},
+    {0, 0, 1.0 / 12.0, -8.0 / 12.0, 0.0, 8.0 / 12.0, -1.0 / 12.0, 0, 0},
+    {0, -1.0 / 60.0, 9.0 / 60.0, -45.0 / 60.0, 0.0, 45.0 / 60.0, -9.0 / 60.0, 1.0 / 60.0, 0},
+    {3.0 / 840.0, -32.0 / 840.0, 168.0 / 840.0, -672.0 / 840.0, 0.0, 672.0 / 840.0,
+     -168.0 / 840.0, 32.0 / 840.0, -3.0 / 840.0}};
+static const double A2[RMAX][2 * RMAX + 1] = {
+    {0, 0, 0, 1.0, -2.0, 1.0, 0, 0, 0},
+    {0, 0, -1.0 / 12.0, 16.0 / 12.0, -30.0 / 12.0, 16.0 / 12.0, -1.0 / 12.0, 0, 0},
+    {0, 2.0 / 180.0, -27.0 / 180.0, 270.0 / 180.0, -490.0 / 180.0, 270.0 / 180.0,
+     -27.0 / 180.0, 2.0 / 180.0, 0},
+    {-9.0 / 5040.0, 128.0 / 5040.0, -1008.0 / 5040.0, 8064.0 / 5040.0, -14350.0 / 5040.0,
+     8064.0 / 5040.0, -1008.0 / 5040.0, 128.0 / 5040.0, -9.0 / 5040.0}};
 
 /* Williamson 2N third-order coefficients: per substep s,
  *   w <- alpha_s w + dt F(f);  f <- f + beta_s w.                       */
@@ -97,23 +112,23 @@ static inline double at(const field_view *v, int64_t i, int64_t j, int64_t k,
 /* Unit offset vectors for axes 0 (x), 1 (y), 2 (z). */
 static const int64_t E[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
 
-/* First derivative along axis a at cell (i, j, k). */
-static double d_first(const field_view *v, const double h[3], int a,
+/* First derivative along axis a at cell (i, j, k), radius r. */
+static double d_first(const field_view *v, const double h[3], int r, int a,
                       int64_t i, int64_t j, int64_t k)
 {
     double acc = 0.0;
-    for (int m = -3; m <= 3; ++m)
-        acc += A1[m + 3] * at(v, i, j, k, m * E[a][0], m * E[a][1], m * E[a][2]);
+    for (int m = -r; m <= r; ++m)
+        acc += A1[r - 1][m + RMAX] * at(v, i, j, k, m * E[a][0], m * E[a][1], m * E[a][2]);
     return acc / h[a];
 }
 
-/* Pure second derivative along axis a at cell (i, j, k). */
-static double d_second(const field_view *v, const double h[3], int a,
+/* Pure second derivative along axis a at cell (i, j, k), radius r. */
+static double d_second(const field_view *v, const double h[3], int r, int a,
                        int64_t i, int64_t j, int64_t k)
 {
     double acc = 0.0;
-    for (int m = -3; m <= 3; ++m)
-        acc += A2[m + 3] * at(v, i, j, k, m * E[a][0], m * E[a][1], m * E[a][2]);
+    for (int m = -r; m <= r; ++m)
+        acc += A2[r - 1][m + RMAX] * at(v, i, j, k, m * E[a][0], m * E[a][1], m * E[a][2]);
     return acc / (h[a] * h[a]);
 }
 
@@ -124,19 +139,19 @@ static double d_second(const field_view *v, const double h[3], int a,
  * and along e_a - e_b, q'' = h_a^2 f_aa - 2 h_a h_b f_ab + h_b^2 f_bb,
  * so f_ab = (g'' - q'') / (4 h_a h_b).  g'' and q'' use the pure
  * second-derivative weights with unit step along their diagonal.         */
-static double d_mixed(const field_view *v, const double h[3], int a, int b,
+static double d_mixed(const field_view *v, const double h[3], int r, int a, int b,
                       int64_t i, int64_t j, int64_t k)
 {
     double gpp = 0.0, qpp = 0.0;
-    for (int m = -3; m <= 3; ++m) {
+    for (int m = -r; m <= r; ++m) {
         int64_t ox_p = m * (E[a][0] + E[b][0]);
         int64_t oy_p = m * (E[a][1] + E[b][1]);
         int64_t oz_p = m * (E[a][2] + E[b][2]);
         int64_t ox_q = m * (E[a][0] - E[b][0]);
         int64_t oy_q = m * (E[a][1] - E[b][1]);
         int64_t oz_q = m * (E[a][2] - E[b][2]);
-        gpp += A2[m + 3] * at(v, i, j, k, ox_p, oy_p, oz_p);
-        qpp += A2[m + 3] * at(v, i, j, k, ox_q, oy_q, oz_q);
+        gpp += A2[r - 1][m + RMAX] * at(v, i, j, k, ox_p, oy_p, oz_p);
+        qpp += A2[r - 1][m + RMAX] * at(v, i, j, k, ox_q, oy_q, oz_q);
     }
     return (gpp - qpp) / (4.0 * h[a] * h[b]);
 }
@@ -157,6 +172,7 @@ static void rhs_cell(const oracle_params *p, const double *f, int64_t i, int64_t
     double h[3];
     grid_spacing(p, h);
     const int64_t cells = (int64_t)p->nx * p->ny * p->nz;
+    const int r = p->radius;
 
     double c[NQ];        /* centre values */
     double g[NQ][3];     /* g[q][a] = d f_q / d x_a */
@@ -165,12 +181,12 @@ static void rhs_cell(const oracle_params *p, const double *f, int64_t i, int64_t
         field_view v = {{p->nx, p->ny, p->nz}, f + q * cells};
         c[q] = at(&v, i, j, k, 0, 0, 0);
         for (int a = 0; a < 3; ++a) {
-            g[q][a] = d_first(&v, h, a, i, j, k);
-            H[q][a][a] = d_second(&v, h, a, i, j, k);
+            g[q][a] = d_first(&v, h, r, a, i, j, k);
+            H[q][a][a] = d_second(&v, h, r, a, i, j, k);
         }
         for (int a = 0; a < 3; ++a)
             for (int b = a + 1; b < 3; ++b) {
-                H[q][a][b] = d_mixed(&v, h, a, b, i, j, k);
+                H[q][a][b] = d_mixed(&v, h, r, a, b, i, j, k);
                 H[q][b][a] = H[q][a][b];
             }
     }
@@ -283,12 +299,12 @@ enum {
     OP_D1X = 0, OP_D1Y, OP_D1Z, OP_D2X, OP_D2Y, OP_D2Z, OP_DXY, OP_DXZ, OP_DYZ
 };
 
-/* Apply one derivative operator to one periodic field of nx*ny*nz cells.
- * Returns 0, or -1 on a bad operator code or size.                      */
+/* Apply one derivative operator of radius r to one periodic field of
+ * nx*ny*nz cells.  Returns 0, or -1 on a bad operator code, radius or size. */
 int oracle_deriv(int32_t nx, int32_t ny, int32_t nz, double lx, double ly, double lz,
-                 const double *f, int32_t op, double *out)
+                 int32_t r, const double *f, int32_t op, double *out)
 {
-    if (nx < 1 || ny < 1 || nz < 1 || op < 0 || op > OP_DYZ)
+    if (nx < 1 || ny < 1 || nz < 1 || op < 0 || op > OP_DYZ || r < 1 || r > RMAX)
         return -1;
     const double h[3] = {lx / nx, ly / ny, lz / nz};
     field_view v = {{nx, ny, nz}, f};
@@ -296,29 +312,35 @@ int oracle_deriv(int32_t nx, int32_t ny, int32_t nz, double lx, double ly, doubl
     for (int64_t k = 0; k < nz; ++k)
         for (int64_t j = 0; j < ny; ++j)
             for (int64_t i = 0; i < nx; ++i) {
-                double r;
+                double d;
                 switch (op) {
-                case OP_D1X: r = d_first(&v, h, 0, i, j, k); break;
-                case OP_D1Y: r = d_first(&v, h, 1, i, j, k); break;
-                case OP_D1Z: r = d_first(&v, h, 2, i, j, k); break;
-                case OP_D2X: r = d_second(&v, h, 0, i, j, k); break;
-                case OP_D2Y: r = d_second(&v, h, 1, i, j, k); break;
-                case OP_D2Z: r = d_second(&v, h, 2, i, j, k); break;
-                case OP_DXY: r = d_mixed(&v, h, 0, 1, i, j, k); break;
-                case OP_DXZ: r = d_mixed(&v, h, 0, 2, i, j, k); break;
-                default:     r = d_mixed(&v, h, 1, 2, i, j, k); break;
+                case OP_D1X: d = d_first(&v, h, r, 0, i, j, k); break;
+                case OP_D1Y: d = d_first(&v, h, r, 1, i, j, k); break;
+                case OP_D1Z: d = d_first(&v, h, r, 2, i, j, k); break;
+                case OP_D2X: d = d_second(&v, h, r, 0, i, j, k); break;
+                case OP_D2Y: d = d_second(&v, h, r, 1, i, j, k); break;
+                case OP_D2Z: d = d_second(&v, h, r, 2, i, j, k); break;
+                case OP_DXY: d = d_mixed(&v, h, r, 0, 1, i, j, k); break;
+                case OP_DXZ: d = d_mixed(&v, h, r, 0, 2, i, j, k); break;
+                default:     d = d_mixed(&v, h, r, 1, 2, i, j, k); break;
                 }
-                out[(k * ny + j) * nx + i] = r;
+                out[(k * ny + j) * nx + i] = d;
             }
     return 0;
 }
 
-/* The weights the oracle uses, for the tests that check them against an
- * independent derivation: a1[7], a2[7] for offsets -3..3.               */
-void oracle_weights(double a1[7], double a2[7])
+/* The weights the oracle uses at radius r, for the tests that check them
+ * against an independent derivation: a1[2r+1], a2[2r+1] for offsets -r..r.
+ * Returns 0, or -1 on a bad radius.                                     */
+int oracle_weights(int32_t r, double *a1, double *a2)
 {
-    memcpy(a1, A1, sizeof A1);
-    memcpy(a2, A2, sizeof A2);
+    if (r < 1 || r > RMAX)
+        return -1;
+    for (int m = -r; m <= r; ++m) {
+        a1[m + r] = A1[r - 1][m + RMAX];
+        a2[m + r] = A2[r - 1][m + RMAX];
+    }
+    return 0;
 }
 
 void oracle_rk3_coeffs(double alpha[3], double beta[3])
@@ -330,7 +352,7 @@ void oracle_rk3_coeffs(double alpha[3], double beta[3])
 /* RHS of all 8 fields at every cell: f and rhs are 8*nx*ny*nz doubles. */
 int oracle_rhs(const oracle_params *p, const double *f, double *rhs)
 {
-    if (!p || p->nx < 1 || p->ny < 1 || p->nz < 1)
+    if (!p || p->nx < 1 || p->ny < 1 || p->nz < 1 || p->radius < 1 || p->radius > RMAX)
         return -1;
     const int64_t nx = p->nx, ny = p->ny, nz = p->nz, cells = nx * ny * nz;
 #pragma omp parallel for schedule(static)
@@ -376,7 +398,8 @@ int oracle_substep_at(const oracle_params *p, int32_t s, const double *f, const 
                       double dt, int64_t ncells, const int64_t *cells, double *out_f,
                       double *out_w)
 {
-    if (!p || s < 0 || s > 2 || (s > 0 && !w) || ncells < 0)
+    if (!p || s < 0 || s > 2 || (s > 0 && !w) || ncells < 0 || p->radius < 1 ||
+        p->radius > RMAX)
         return -1;
     const int64_t nx = p->nx, ny = p->ny, nz = p->nz, n = nx * ny * nz;
     for (int64_t t = 0; t < ncells; ++t)

@@ -117,6 +117,23 @@ def test_rhs_sixth_order_convergence(oracle_mod, analytic):
     assert np.all(r1 > 35) and np.all((r2 > 50) & (r2 < 80)), (r1, r2)
 
 
+@pytest.mark.parametrize("order", [2, 4, 8])
+def test_rhs_order_2r_convergence(oracle_mod, analytic, order):
+    """The whole right-hand side converges at the stencil's order 2r
+    (Section 4: orders 2, 4, 6 and 8) to the symbolic one."""
+    ffn, rfn = analytic
+    errs = []
+    for n in (32, 64):
+        f = _eval_on_grid(ffn, (n, n, n))
+        exact = _eval_on_grid(rfn, (n, n, n))
+        got = oracle_mod.rhs(f, _params(oracle_mod, (n, n, n), order=order))
+        errs.append([np.max(np.abs(got[q] - exact[q])) / np.max(np.abs(exact[q])) for q in range(8)])
+    errs = np.array(errs)
+    ratio = errs[0] / errs[1]
+    rate = 2.0 ** order
+    assert np.all((ratio > 0.75 * rate) & (ratio < 1.3 * rate)), (order, ratio, errs)
+
+
 def test_rhs_convergence_anisotropic_box(oracle_mod):
     """Unequal box lengths and cell counts per axis (fields periodic on it)."""
     L = (TWO_PI, 2 * TWO_PI, TWO_PI)

@@ -72,6 +72,48 @@ def time_segmented(S, torch, bufs, cur, w, comp, dt, steps, cells):
                 gcups=round(3 * cells * steps / (ms * 1e-3) / 1e9, 4))
 
 
+def order_study(mhd, inputs, torch, steps=5, warmup=1, name="sub256"):
+    """Time per cell per RK3 step for the stencil orders 2, 4, 6 and 8 at
+    256^3 (the single-GPU part of the paper's order study, Section 5), FP64
+    and FP32C, each with the library's kernel for that order and precision
+    (mhd_step, halo fill included)."""
+    wl = inputs.WORKLOADS[name]
+    n = wl["shape"]
+    cells = math.prod(n)
+    out = {"workload": WORKLOAD_TEXT[name], "steps": steps}
+    for prec in ("f64", "f32c"):
+        per = {}
+        for order in (2, 4, 6, 8):
+            S = mhd.Solver(*n, prec, order=order)
+            bufs = [S.upload_fields(inputs.workload_fields(name)), S.empty()]
+            w = S.zeros()
+            comp = S.zeros() if prec == "f32c" else None
+            cur = S.step(bufs, 0, w, comp, wl["dt"], warmup)
+            torch.cuda.synchronize()
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            stream = torch.cuda.current_stream()
+            t0.record(stream)
+            cur = S.step(bufs, cur, w, comp, wl["dt"], steps)
+            t1.record(stream)
+            torch.cuda.synchronize()
+            ms = t0.elapsed_time(t1) / steps
+            nonfinite = S.reduce(bufs[cur], 0, "nonfinite")
+            gbs = cells * sum(BYTES_PER_CELL[prec]) / (ms * 1e-3) / 1e9
+            per[str(order)] = {"kernel": KERNEL_SYMBOL[S.kernel], "ms_per_step": round(ms, 4),
+                               "ns_per_cell_step": round(ms * 1e6 / cells, 4),
+                               "gcups": round(3 * cells / (ms * 1e-3) / 1e9, 3),
+                               "roofline_frac": round(gbs / HBM_PEAK_GBS, 4),
+                               "nonfinite": nonfinite}
+            S.close()
+            del bufs, w, comp
+            torch.cuda.empty_cache()
+            print(f"# order {order} {prec}: {json.dumps(per[str(order)])}", file=sys.stderr,
+                  flush=True)
+        out[prec] = per
+    return out
+
+
 def run_precision(mhd, inputs, torch, name, prec, steps, warmup, kernel, segmented=False):
     wl = inputs.WORKLOADS[name]
     n = wl["shape"]
@@ -190,6 +232,8 @@ def main():
     ap.add_argument("--no-segmented", action="store_true",
                     help="skip the timing of the segmented (inner/outer, packed halo "
                          "exchange) step")
+    ap.add_argument("--no-order-study", action="store_true",
+                    help="skip the timing of stencil orders 2, 4, 6 and 8 at 256^3")
     ap.add_argument("--kernel", default=None, choices=["split", "tiled", "direct"],
                     help="fused-substep kernel (default: the library's default for each "
                          "precision: split for f64, tiled otherwise)")
@@ -248,6 +292,8 @@ def main():
     segs = {prec: rr["segmented"] for prec, rr in results.items() if rr["segmented"]}
     if segs:
         line["segmented"] = segs
+    if not args.no_order_study:
+        line["order_study"] = order_study(mhd, inputs, torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(inputs, inputs.WORKLOADS["prec512"])
     print(json.dumps(line), flush=True)

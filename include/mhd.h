@@ -1,14 +1,15 @@
 /*
- * mhd.h -- C ABI of the fused sixth-order MHD RK3 substep on one MI355X (gfx950).
+ * mhd.h -- C ABI of the fused high-order MHD RK3 substep on one MI355X (gfx950).
  *
  * The operations follow Pekkila et al., "Scalable communication for
  * high-order stencil computations using CUDA-aware MPI":
  *   - the grid is the computational domain of n_i cells per axis surrounded
- *     by a halo of r = 3 cells (Section 2, Eq. 1; r = 3 for sixth order);
+ *     by a halo of r cells, r the stencil radius (Section 2, Eq. 1): order
+ *     k = 2r of 2, 4, 6 (the default) or 8 (Section 4);
  *   - the periodic halo mapping is s' = ((s - r) mod n) + r (Section 3.3);
  *   - the right-hand side is the non-ideal MHD system of Appendix B
- *     (Eqs. B.1-B.4, fields of Table B.1) with sixth-order central
- *     differences on the stencil set of Section 4, Eq. (stencil-fd);
+ *     (Eqs. B.1-B.4, fields of Table B.1) with central differences of
+ *     order 2r on the stencil set of Section 4, Eq. (stencil-fd);
  *   - time integration is Williamson's third-order low-storage (2N)
  *     Runge-Kutta scheme (Section 4); one substep is one iterative-stencil
  *     iteration and a full step is three of them (Section 5);
@@ -71,19 +72,26 @@ enum mhd_reduce_op {
 };
 
 /* ---------------------------------------------------------------- types */
-/* Which fused-substep kernel runs (same results up to rounding order). */
+/* Which fused-substep kernel runs (same results up to rounding order).
+ * Orders: DIRECT every order and precision; TILED every order except
+ * order 8 in MHD_F64 (its LDS ring would exceed a CU's 160 KB); SPLIT
+ * order 6 only.  AUTO: init picks the fastest available for the precision
+ * and order (MHD_F64: SPLIT at order 6, TILED at orders 2 and 4, DIRECT at
+ * order 8; otherwise TILED) and reports it in mhd_layout.kernel. */
 enum mhd_kernel {
     MHD_KERNEL_TILED = 0,  /* LDS-tiled z-marching kernel */
     MHD_KERNEL_DIRECT = 1, /* one thread per cell, stencil read from global memory */
-    MHD_KERNEL_SPLIT = 2   /* LDS-tiled z-march, two threads per cell splitting the
+    MHD_KERNEL_SPLIT = 2,  /* LDS-tiled z-march, two threads per cell splitting the
                               fields (velocity side / entropy-induction side) */
+    MHD_KERNEL_AUTO = 3
 };
 
 typedef struct mhd_config {
     int32_t nx, ny, nz;   /* computational domain n_i >= 1 (interior cells per axis) */
     int32_t precision;    /* enum mhd_precision */
     int32_t kernel;       /* enum mhd_kernel */
-    int32_t reserved_;    /* must be 0 */
+    int32_t order;        /* stencil order k = 2r: 2, 4, 6 or 8 (Section 4); the
+                             halo and the stencil radius are r = order/2 */
     double lx, ly, lz;    /* box lengths; h_i = l_i / n_i (vertex-centred cells) */
     /* Appendix B constants: adiabatic sound speed at ln rho = lnrho0, s = 0;
      * adiabatic index; heat capacity at constant pressure; reference ln rho;
@@ -93,18 +101,21 @@ typedef struct mhd_config {
     double bext[3];       /* uniform field added to curl A (zero by default) */
 } mhd_config;
 
-/* Geometry of every buffer the caller allocates (f, w, comp).  Element
- * (q, z, y, x) of the padded grid, 0 <= x < mx etc., is at element index
- * q*field_stride + (z*my + y)*mx + x; interior cell (i, j, k) is at
- * padded (i + 3, j + 3, k + 3), i.e. interior_offset + (k*my + j)*mx + i
- * within its field.  A buffer holds total_elems elements of elem_size
- * bytes and must be at least 256-byte aligned. */
+/* Geometry of every buffer the caller allocates (f, w, comp), with a halo
+ * of r = order/2 cells.  Element (q, z, y, x) of the padded grid,
+ * 0 <= x < mx etc., is at element index q*field_stride + (z*my + y)*mx + x;
+ * interior cell (i, j, k) is at padded (i + r, j + r, k + r), i.e.
+ * interior_offset + (k*my + j)*mx + i within its field.  A buffer holds
+ * total_elems elements of elem_size bytes and must be at least 256-byte
+ * aligned. */
 typedef struct mhd_layout {
-    int64_t mx, my, mz;         /* padded extents n_i + 6 */
+    int64_t mx, my, mz;         /* padded extents n_i + 2r */
     int64_t field_stride;       /* elements between fields (>= mx*my*mz) */
     int64_t elem_size;          /* 8 for MHD_F64, 4 otherwise */
-    int64_t interior_offset;    /* (3*my + 3)*mx + 3 */
+    int64_t interior_offset;    /* (r*my + r)*mx + r */
     int64_t total_elems;        /* 8 * field_stride */
+    int64_t halo;               /* r */
+    int64_t kernel;             /* the fused kernel in use (enum mhd_kernel, never AUTO) */
 } mhd_layout;
 
 typedef struct mhd_ctx mhd_ctx;
@@ -119,9 +130,8 @@ typedef struct mhd_box {
 
 /* Fill *cfg with the defaults for an n = (nx, ny, nz) grid: l = 2*pi per
  * axis, cs0 = 1, gamma = 5/3, cp = 1, lnrho0 = 0, mu0 = 1,
- * nu = eta = 5e-3, zeta = 0, K = 5e-3, bext = 0, kernel = MHD_KERNEL_SPLIT for
- * MHD_F64 and MHD_KERNEL_TILED otherwise (the faster of each).
- * Never fails. */
+ * nu = eta = 5e-3, zeta = 0, K = 5e-3, bext = 0, order = 6,
+ * kernel = MHD_KERNEL_AUTO.  Never fails. */
 void mhd_config_default(mhd_config *cfg, int32_t nx, int32_t ny, int32_t nz,
                         int32_t precision);
 
@@ -131,7 +141,8 @@ void mhd_config_default(mhd_config *cfg, int32_t nx, int32_t ny, int32_t nz,
  * than 2^31 - 4096 cells or of 4 GiB or more (the kernels address within a
  * field with 32-bit offsets), ny or nz above 65535, non-finite or
  * non-positive lengths, gamma <= 1,
- * cp <= 0, mu0 == 0, unknown precision or kernel, reserved_ != 0),
+ * cp <= 0, mu0 == 0, unknown precision or kernel, order not in
+ * {2, 4, 6, 8}, a kernel not built for the order and precision),
  * MHD_ERR_NO_DEVICE, MHD_ERR_DEVICE, MHD_ERR_NOMEM. */
 int mhd_init(const mhd_config *cfg, mhd_ctx **out, mhd_layout *layout);
 
@@ -170,25 +181,25 @@ int mhd_step(mhd_ctx *ctx, void *const f[2], int32_t *cur, void *w, void *comp, 
              int32_t nsteps, void *stream);
 
 /* ------------------------------------------------ segmented iteration
- * The iteration of Section 3.3 (Fig. iteration): pack the 6 side and 12
- * edge segments of the 3-cell boundary layer (corners are not needed by
+ * The iteration of Section 3.3 (Fig. concurrency): pack the 6 side and 12
+ * edge segments of the r-cell boundary layer (corners are not needed by
  * the stencil, Section 5) into a send buffer, exchange them with the
- * neighbouring subdomains while the inner box (cells at least 3 from every
+ * neighbouring subdomains while the inner box (cells at least r from every
  * face, which read no halo) is updated, unpack the received segments into
  * the halo, then update the outer shell.  On one GPU with periodic
  * boundaries the neighbour in every direction is the subdomain itself, so
  * the exchange is a device-to-device copy of each segment to the slot of
  * the opposite direction (where several GPUs would exchange peer to peer).
- * Every entry point here requires nx, ny, nz >= 3 (else MHD_ERR_INVALID). */
+ * Every entry point here requires nx, ny, nz >= r (else MHD_ERR_INVALID). */
 
 /* Elements of one packed buffer (all 8 fields, 18 segments; bytes =
  * elements * layout.elem_size).  Segment order: directions d in
  * {-1,0,1}^3 with one or two non-zero components, z slowest then y then x;
- * each segment [field][z][y][x] over its extents (3 along every non-zero
+ * each segment [field][z][y][x] over its extents (r along every non-zero
  * component of d, n along the others).  -1 for a NULL ctx. */
 int64_t mhd_halo_segment_elems(const mhd_ctx *ctx);
 
-/* Pack the boundary layer of `fields` (interior cells within 3 of the face
+/* Pack the boundary layer of `fields` (interior cells within r of the face
  * or edge in direction d, for every segment d) into `sendbuf` (device,
  * mhd_halo_segment_elems elements of the storage type). */
 int mhd_halo_pack(mhd_ctx *ctx, const void *fields, void *sendbuf, void *stream);
@@ -206,7 +217,7 @@ int mhd_halo_exchange_self(mhd_ctx *ctx, void *fields, void *sendbuf, void *recv
 
 /* mhd_rk3_substep restricted to the interior cells of `box`; every other
  * cell of f_out, w and comp is left untouched.  Precondition: every cell
- * within 3 of the box (halo included) holds current values.  Errors: as
+ * within r of the box (halo included) holds current values.  Errors: as
  * mhd_rk3_substep, and MHD_ERR_INVALID for a NULL or out-of-range box. */
 int mhd_rk3_substep_box(mhd_ctx *ctx, int32_t s, const mhd_box *box, const void *f_in,
                         void *f_out, void *w, void *comp, double dt, void *stream);
@@ -215,13 +226,13 @@ int mhd_rk3_substep_box(mhd_ctx *ctx, int32_t s, const mhd_box *box, const void 
  * segments of the input are packed on `stream`; the exchange and unpack
  * (as mhd_halo_exchange_self) run on `comm_stream` while the inner box is
  * updated on `stream`; the six outer slabs follow on `stream` once the halo
- * is in.  The inner box keeps 3 cells from the z faces, 32 from the x faces
+ * is in.  The inner box keeps r cells from the z faces, 32 from the x faces
  * and 8 from the y faces (whole tiles of the fused kernels); on return all
  * work of `comm_stream` is ordered before the rest of `stream`.  Results are
  * identical to mhd_step's, bit for bit.  sendbuf, recvbuf: device buffers of
  * mhd_halo_segment_elems elements.  Calls on one context must not overlap.
  * Errors: as mhd_step, and MHD_ERR_INVALID for missing or equal buffers or a
- * grid below 3 cells. */
+ * grid below r cells. */
 int mhd_step_segmented(mhd_ctx *ctx, void *const f[2], int32_t *cur, void *w, void *comp,
                        double dt, int32_t nsteps, void *sendbuf, void *recvbuf, void *stream,
                        void *comm_stream);

@@ -59,10 +59,11 @@ int validate(const mhd_config* c)
     if (!c) return MHD_ERR_INVALID;
     if (c->nx < 1 || c->ny < 1 || c->nz < 1) return MHD_ERR_INVALID;
     if (c->precision < MHD_F64 || c->precision > MHD_F32) return MHD_ERR_INVALID;
-    if (c->kernel != MHD_KERNEL_TILED && c->kernel != MHD_KERNEL_DIRECT &&
-        c->kernel != MHD_KERNEL_SPLIT)
+    if (c->kernel < MHD_KERNEL_TILED || c->kernel > MHD_KERNEL_AUTO) return MHD_ERR_INVALID;
+    if (c->order != 2 && c->order != 4 && c->order != 6 && c->order != 8) return MHD_ERR_INVALID;
+    if (c->kernel == MHD_KERNEL_SPLIT && c->order != 6) return MHD_ERR_INVALID;
+    if (c->kernel == MHD_KERNEL_TILED && c->precision == MHD_F64 && c->order == 8)
         return MHD_ERR_INVALID;
-    if (c->reserved_ != 0) return MHD_ERR_INVALID;
     if (!finite_pos(c->lx) || !finite_pos(c->ly) || !finite_pos(c->lz)) return MHD_ERR_INVALID;
     if (!isfinite(c->gamma) || c->gamma <= 1.0) return MHD_ERR_INVALID;
     if (!finite_pos(c->cp) || !isfinite(c->cs0) || !isfinite(c->lnrho0)) return MHD_ERR_INVALID;
@@ -73,7 +74,7 @@ int validate(const mhd_config* c)
     for (double v : c->bext)
         if (!isfinite(v)) return MHD_ERR_INVALID;
     // every padded field must be addressable with 32-bit offsets
-    const int64_t mx = c->nx + 6, my = c->ny + 6, mz = c->nz + 6;
+    const int64_t mx = c->nx + c->order, my = c->ny + c->order, mz = c->nz + c->order;
     if (mx * my * mz > (int64_t)INT32_MAX - 4096) return MHD_ERR_INVALID;
     // and every padded field must be byte-addressable with 32-bit offsets
     const int64_t elem = c->precision == MHD_F64 ? 8 : 4;
@@ -126,7 +127,7 @@ int one_substep(mhd_ctx* ctx, int s, const void* f_in, void* f_out, void* w, voi
 // The interior split of the segmented iteration (Section 3.3): the inner box,
 // which reads no halo, and the six slabs of the outer shell (z faces over the
 // whole plane, then y faces, then x faces), disjoint and together the whole
-// interior.  The shell is R planes thick at the z faces but a whole tile
+// interior.  The shell is r planes thick at the z faces but a whole tile
 // (OUTER_X columns, OUTER_Y rows) at the x and y faces: the fused kernels
 // march in z over 32 x 8 tiles, and a slab thinner than a tile would leave
 // most of each tile's lanes idle.  Empty boxes are skipped by one_substep.
@@ -136,7 +137,7 @@ void inner_outer(const Grid& g, Box& inner, Box outer[6])
     auto lo = [](int n, int w) { return n < w ? n : w; };
     auto hi = [&](int n, int w) { return n - w > lo(n, w) ? n - w : lo(n, w); };
     const int xa = lo(g.nx, OUTER_X), xb = hi(g.nx, OUTER_X), ya = lo(g.ny, OUTER_Y),
-              yb = hi(g.ny, OUTER_Y), za = lo(g.nz, R), zb = hi(g.nz, R);
+              yb = hi(g.ny, OUTER_Y), za = lo(g.nz, g.r), zb = hi(g.nz, g.r);
     inner = Box{xa, xb, ya, yb, za, zb};
     outer[0] = Box{0, g.nx, 0, g.ny, 0, za};
     outer[1] = Box{0, g.nx, 0, g.ny, zb, g.nz};
@@ -253,8 +254,8 @@ void mhd_config_default(mhd_config* cfg, int32_t nx, int32_t ny, int32_t nz, int
     cfg->zeta = 0.0;
     cfg->eta = 5e-3;
     cfg->K = 5e-3;
-    // the faster kernel of each precision at 512^3 on MI355X
-    cfg->kernel = precision == MHD_F64 ? MHD_KERNEL_SPLIT : MHD_KERNEL_TILED;
+    cfg->order = 6;
+    cfg->kernel = MHD_KERNEL_AUTO;
 }
 
 const char* mhd_strerror(int status)
@@ -289,15 +290,28 @@ int mhd_init(const mhd_config* cfg, mhd_ctx** out, mhd_layout* layout)
     ctx->cfg = *cfg;
     ctx->device = dev;
 
+    // AUTO: the fastest kernel built for the precision and order (measured
+    // at 512^3 and 256^3 on MI355X)
+    if (cfg->kernel == MHD_KERNEL_AUTO) {
+        if (cfg->precision != MHD_F64)
+            ctx->cfg.kernel = MHD_KERNEL_TILED;
+        else
+            ctx->cfg.kernel = cfg->order == 6   ? MHD_KERNEL_SPLIT
+                              : cfg->order == 8 ? MHD_KERNEL_DIRECT
+                                                : MHD_KERNEL_TILED;
+    }
+    const int r = cfg->order / 2;
     mhd_layout& L = ctx->lay;
-    L.mx = cfg->nx + 2 * R;
-    L.my = cfg->ny + 2 * R;
-    L.mz = cfg->nz + 2 * R;
+    L.mx = cfg->nx + 2 * r;
+    L.my = cfg->ny + 2 * r;
+    L.mz = cfg->nz + 2 * r;
     const int64_t cells = L.mx * L.my * L.mz;
     L.field_stride = (cells + 63) / 64 * 64;
     L.elem_size = cfg->precision == MHD_F64 ? 8 : 4;
-    L.interior_offset = (R * L.my + R) * L.mx + R;
+    L.interior_offset = (r * L.my + r) * L.mx + r;
     L.total_elems = NQ * L.field_stride;
+    L.halo = r;
+    L.kernel = ctx->cfg.kernel;
 
     Grid& g = ctx->grid;
     g.nx = cfg->nx;
@@ -309,6 +323,7 @@ int mhd_init(const mhd_config* cfg, mhd_ctx** out, mhd_layout* layout)
     g.fstride = L.field_stride;
     g.mxy = (int)(L.mx * L.my);
     g.interior = (int)L.interior_offset;
+    g.r = r;
 
     Phys& P = ctx->phys;
     P.inv_h[0] = cfg->nx / cfg->lx;
@@ -424,7 +439,8 @@ int64_t mhd_halo_segment_elems(const mhd_ctx* ctx)
 namespace {
 bool exchange_ok(const mhd_ctx* ctx)
 {
-    return ctx->grid.nx >= R && ctx->grid.ny >= R && ctx->grid.nz >= R;
+    const Grid& g = ctx->grid;
+    return g.nx >= g.r && g.ny >= g.r && g.nz >= g.r;
 }
 }  // namespace
 

@@ -1,14 +1,14 @@
 // Packed halo segments for the segmented (inner / outer) iteration of
-// Section 3.3: the 6 side and 12 edge segments of a subdomain's 3-cell
+// Section 3.3: the 6 side and 12 edge segments of a subdomain's r-cell
 // boundary layer (corners are not read by the stencil, Section 5), packed
 // into one contiguous buffer, and the reverse scatter of received segments
 // into the halo.
 //
 // Segment d, a direction in {-1, 0, 1}^3 with one or two non-zero
-// components, covers per axis a:  d_a = -1: cells [0, 3),  0: [0, n_a),
-// +1: [n_a - 3, n_a)  of the interior (what the neighbour at offset d needs),
-// and its received counterpart fills the halo cells  d_a = -1: [-3, 0),
-// 0: [0, n_a), +1: [n_a, n_a + 3).  Within a segment the layout is
+// components, covers per axis a:  d_a = -1: cells [0, r),  0: [0, n_a),
+// +1: [n_a - r, n_a)  of the interior (what the neighbour at offset d needs),
+// and its received counterpart fills the halo cells  d_a = -1: [-r, 0),
+// 0: [0, n_a), +1: [n_a, n_a + r); r is the halo width.  Within a segment the layout is
 // [field][z][y][x] over the segment's extents; segments follow each other in
 // the fixed order of seg_table.
 #include "mhd_internal.hpp"
@@ -29,7 +29,7 @@ SegTable seg_table(const Grid& g)
                 int64_t cells = 1;
                 for (int a = 0; a < 3; ++a) {
                     t.dir[k][a] = d[a];
-                    t.len[k][a] = d[a] == 0 ? n[a] : R;
+                    t.len[k][a] = d[a] == 0 ? n[a] : g.r;
                     cells *= t.len[k][a];
                 }
                 t.off[k] = off;
@@ -69,8 +69,8 @@ SegLaunch seg_launch(const Grid& g, const SegTable& t)
         for (int a = 0; a < 3; ++a) {
             const int d = t.dir[k][a];
             L.len[k][a] = t.len[k][a];
-            L.src[k][a] = d == 0 ? 0 : d < 0 ? 0 : n[a] - R;
-            L.dst[k][a] = d == 0 ? 0 : d < 0 ? -R : n[a];
+            L.src[k][a] = d == 0 ? 0 : d < 0 ? 0 : n[a] - g.r;
+            L.dst[k][a] = d == 0 ? 0 : d < 0 ? -g.r : n[a];
         }
     }
     L.blk[NSEG] = blocks;

@@ -10,16 +10,18 @@
 
 namespace mhd {
 
-constexpr int R = 3;   // stencil radius (sixth order, Section 4)
-constexpr int NQ = 8;  // fields of Table B.1
+constexpr int RMAX = 4;  // largest stencil radius (eighth order, Section 4)
+constexpr int NQ = 8;    // fields of Table B.1
 
-// Grid geometry as the kernels see it.
+// Grid geometry as the kernels see it.  The halo is r cells wide, r the
+// stencil radius (order 2r).
 struct Grid {
     int nx, ny, nz;
-    int mx, my, mz;
+    int mx, my, mz;   // n_i + 2r
     int64_t fstride;  // elements between fields
     int mxy;          // mx*my (one padded plane; < 2^31 for every supported size)
-    int interior;     // (3*my + 3)*mx + 3
+    int interior;     // (r*my + r)*mx + r
+    int r;            // halo width = stencil radius
 };
 
 // A sub-box of the interior, half-open in interior cell indices:
@@ -44,15 +46,37 @@ struct Phys {
 constexpr double RK_ALPHA[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
 constexpr double RK_BETA[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
 
-// Sixth-order central weights, expressed as multipliers of differences:
-// D1 f = [45 d1 - 9 d2 + d3] / (60 h),    d_m = f(+m) - f(-m)
-// D2 f = [-490 f0 + 270 s1 - 27 s2 + 2 s3] / (180 h^2),  s_m = f(+m) + f(-m)
-// Dab f = [270 e1 - 27 e2 + 2 e3] / (720 h_a h_b), e_m = P_m - Q_m with
-//   P_m = f(+m,+m) + f(-m,-m), Q_m = f(+m,-m) + f(-m,+m) on the (a,b) plane.
-constexpr double C1_1 = 45.0 / 60.0, C1_2 = -9.0 / 60.0, C1_3 = 1.0 / 60.0;
-constexpr double C2_0 = -490.0 / 180.0, C2_1 = 270.0 / 180.0, C2_2 = -27.0 / 180.0,
-                 C2_3 = 2.0 / 180.0;
-constexpr double CM_1 = 270.0 / 720.0, CM_2 = -27.0 / 720.0, CM_3 = 2.0 / 720.0;
+// Central weights of order 2r (Section 4 lists r = 1..4), as integer
+// multipliers of symmetric differences over one denominator per kind:
+//   D1 f  = sum_m W1(r,m) d_m / (DEN1(r) h),             d_m = f(+m) - f(-m)
+//   D2 f  = [W2(r,0) f0 + sum_m W2(r,m) s_m] / (DEN2(r) h^2),  s_m = f(+m) + f(-m)
+//   Dab f = sum_m W2(r,m) e_m / (4 DEN2(r) h_a h_b),  e_m = P_m - Q_m with
+//     P_m = f(+m,+m) + f(-m,-m), Q_m = f(+m,-m) + f(-m,+m) on the (a,b) plane
+// (the mixed form is the difference of the second differences along the two
+// diagonals of the plane, Eq. stencil-fd).  m = 1..r.
+__host__ __device__ constexpr double W1(int r, int m)
+{
+    return r == 1 ? (m == 1 ? 1.0 : 0.0)
+         : r == 2 ? (m == 1 ? 8.0 : m == 2 ? -1.0 : 0.0)
+         : r == 3 ? (m == 1 ? 45.0 : m == 2 ? -9.0 : m == 3 ? 1.0 : 0.0)
+                  : (m == 1 ? 672.0 : m == 2 ? -168.0 : m == 3 ? 32.0 : m == 4 ? -3.0 : 0.0);
+}
+__host__ __device__ constexpr double DEN1(int r)
+{
+    return r == 1 ? 2.0 : r == 2 ? 12.0 : r == 3 ? 60.0 : 840.0;
+}
+__host__ __device__ constexpr double W2(int r, int m)
+{
+    return r == 1 ? (m == 0 ? -2.0 : m == 1 ? 1.0 : 0.0)
+         : r == 2 ? (m == 0 ? -30.0 : m == 1 ? 16.0 : m == 2 ? -1.0 : 0.0)
+         : r == 3 ? (m == 0 ? -490.0 : m == 1 ? 270.0 : m == 2 ? -27.0 : m == 3 ? 2.0 : 0.0)
+                  : (m == 0 ? -14350.0 : m == 1 ? 8064.0 : m == 2 ? -1008.0 : m == 3 ? 128.0
+                     : m == 4 ? -9.0 : 0.0);
+}
+__host__ __device__ constexpr double DEN2(int r)
+{
+    return r == 1 ? 1.0 : r == 2 ? 12.0 : r == 3 ? 180.0 : 5040.0;
+}
 
 // Everything the right-hand side of Eqs. B.1-B.4 reads at one cell.
 // R: the arithmetic type of the physics (double, or float for FP32 storage).
@@ -190,7 +214,7 @@ __device__ __forceinline__ float kahan_add(float f, float y, float& c)
 
 // The 6 side and 12 edge segments of a subdomain's boundary layer (the
 // packed halo exchange of Section 3.3): per segment its direction d, its
-// extents (3 along every non-zero component of d, n_a otherwise) and its
+// extents (r along every non-zero component of d, n_a otherwise) and its
 // element offset in a packed buffer of all 8 fields.  Segment NSEG-1-k has
 // direction -d of segment k.
 constexpr int NSEG = 18;

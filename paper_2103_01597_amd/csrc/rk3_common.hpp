@@ -1,5 +1,5 @@
 // Pieces shared by the fused RHS + RK3 kernels: precision traits, the
-// unscaled sixth-order stencil sums (Section 4, Eq. stencil-fd) and the
+// unscaled stencil sums of order 2r (Section 4, Eq. stencil-fd) and the
 // per-cell 2N update with its FP32 compensated variant.
 #pragma once
 
@@ -30,37 +30,40 @@ struct Prec<MHD_F32> {
     using D2 = float;
 };
 
-// First derivative times h along a stride st.
-template <typename A, typename T>
+// First derivative times h along a stride st (radius RAD).
+template <typename A, int RAD, typename T>
 __device__ __forceinline__ A deriv1(const T* p, int st)
 {
-    const A d1 = A(p[st]) - A(p[-st]);
-    const A d2 = A(p[2 * st]) - A(p[-2 * st]);
-    const A d3 = A(p[3 * st]) - A(p[-3 * st]);
-    return A(C1_1) * d1 + A(C1_2) * d2 + A(C1_3) * d3;
+    A acc = A(W1(RAD, 1) / DEN1(RAD)) * (A(p[st]) - A(p[-st]));
+#pragma unroll
+    for (int m = 2; m <= RAD; ++m) acc += A(W1(RAD, m) / DEN1(RAD)) * (A(p[m * st]) - A(p[-m * st]));
+    return acc;
 }
 
 // Pure second derivative times h^2 along a stride st.
-template <typename A, typename T>
+template <typename A, int RAD, typename T>
 __device__ __forceinline__ A deriv2(const T* p, int st)
 {
-    const A s1 = A(p[st]) + A(p[-st]);
-    const A s2 = A(p[2 * st]) + A(p[-2 * st]);
-    const A s3 = A(p[3 * st]) + A(p[-3 * st]);
-    return A(C2_0) * A(p[0]) + A(C2_1) * s1 + A(C2_2) * s2 + A(C2_3) * s3;
+    A acc = A(W2(RAD, 0) / DEN2(RAD)) * A(p[0]);
+#pragma unroll
+    for (int m = 1; m <= RAD; ++m) acc += A(W2(RAD, m) / DEN2(RAD)) * (A(p[m * st]) + A(p[-m * st]));
+    return acc;
 }
 
 // Mixed second derivative times h_a h_b from the diagonals of the plane
 // spanned by strides sa, sb: difference of the second differences along
 // (+1, +1) and (+1, -1), divided by 4.
-template <typename A, typename T>
+template <typename A, int RAD, typename T>
 __device__ __forceinline__ A derivm(const T* p, int sa, int sb)
 {
     const int pp = sa + sb, pm = sa - sb;
-    const A e1 = (A(p[pp]) + A(p[-pp])) - (A(p[pm]) + A(p[-pm]));
-    const A e2 = (A(p[2 * pp]) + A(p[-2 * pp])) - (A(p[2 * pm]) + A(p[-2 * pm]));
-    const A e3 = (A(p[3 * pp]) + A(p[-3 * pp])) - (A(p[3 * pm]) + A(p[-3 * pm]));
-    return A(CM_1) * e1 + A(CM_2) * e2 + A(CM_3) * e3;
+    A acc = A(0);
+#pragma unroll
+    for (int m = 1; m <= RAD; ++m) {
+        const A e = (A(p[m * pp]) + A(p[-m * pp])) - (A(p[m * pm]) + A(p[-m * pm]));
+        acc += A(W2(RAD, m) / (4.0 * DEN2(RAD))) * e;
+    }
+    return acc;
 }
 
 // 2N update of one cell of one field, by value: returns the new register

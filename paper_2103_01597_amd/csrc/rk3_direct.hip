@@ -1,5 +1,6 @@
 // Fused RHS + RK3 substep, direct form: one thread per interior cell, every
-// stencil point read from global memory (the L1/L2 caches catch the reuse).
+// stencil point read from global memory (the L1/L2 caches catch the reuse),
+// for every stencil order 2r, r = 1..4.
 // It is the plain baseline next to the LDS-tiled z-marching kernel and the
 // path used for grids too small for that kernel's tiles.
 //
@@ -13,7 +14,7 @@
 namespace mhd {
 namespace {
 
-template <int PREC>
+template <int PREC, int RAD>
 __global__ __launch_bounds__(256) void k_rk3_direct(Grid g, Phys P, Box bx, int s,
                                                     const typename Prec<PREC>::T* __restrict__ fin,
                                                     typename Prec<PREC>::T* __restrict__ fout,
@@ -52,31 +53,31 @@ __global__ __launch_bounds__(256) void k_rk3_direct(Grid g, Phys P, Box bx, int 
     const D2 ih2[3] = {ih2x, ih2y, ih2z};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        d.gl[a] = deriv1<Rt>(F[0], st[a]) * ih[a];
-        d.gs[a] = deriv1<Rt>(F[4], st[a]) * ih[a];
+        d.gl[a] = deriv1<Rt, RAD>(F[0], st[a]) * ih[a];
+        d.gs[a] = deriv1<Rt, RAD>(F[4], st[a]) * ih[a];
 #pragma unroll
         for (int b = 0; b < 3; ++b)
-            d.gu[b][a] = deriv1<Rt>(F[1 + b], st[a]) * ih[a];
+            d.gu[b][a] = deriv1<Rt, RAD>(F[1 + b], st[a]) * ih[a];
     }
-    d.dAz_dy = deriv1<Rt>(F[7], sy) * ihy;
-    d.dAy_dz = deriv1<Rt>(F[6], sz) * ihz;
-    d.dAx_dz = deriv1<Rt>(F[5], sz) * ihz;
-    d.dAz_dx = deriv1<Rt>(F[7], sx) * ihx;
-    d.dAy_dx = deriv1<Rt>(F[6], sx) * ihx;
-    d.dAx_dy = deriv1<Rt>(F[5], sy) * ihy;
+    d.dAz_dy = deriv1<Rt, RAD>(F[7], sy) * ihy;
+    d.dAy_dz = deriv1<Rt, RAD>(F[6], sz) * ihz;
+    d.dAx_dz = deriv1<Rt, RAD>(F[5], sz) * ihz;
+    d.dAz_dx = deriv1<Rt, RAD>(F[7], sx) * ihx;
+    d.dAy_dx = deriv1<Rt, RAD>(F[6], sx) * ihx;
+    d.dAx_dy = deriv1<Rt, RAD>(F[5], sy) * ihy;
 
     D2 sec[NQ][3];  // pure second derivatives D_aa of every field
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
 #pragma unroll
         for (int a = 0; a < 3; ++a)
-            sec[q][a] = deriv2<D2>(F[q], st[a]) * ih2[a];
-    const D2 uxy = derivm<D2>(F[1], sx, sy) * ihxy, uyx = derivm<D2>(F[2], sx, sy) * ihxy;
-    const D2 uxz = derivm<D2>(F[1], sx, sz) * ihxz, uzx = derivm<D2>(F[3], sx, sz) * ihxz;
-    const D2 uyz = derivm<D2>(F[2], sy, sz) * ihyz, uzy = derivm<D2>(F[3], sy, sz) * ihyz;
-    const D2 axy = derivm<D2>(F[5], sx, sy) * ihxy, ayx = derivm<D2>(F[6], sx, sy) * ihxy;
-    const D2 axz = derivm<D2>(F[5], sx, sz) * ihxz, azx = derivm<D2>(F[7], sx, sz) * ihxz;
-    const D2 ayz = derivm<D2>(F[6], sy, sz) * ihyz, azy = derivm<D2>(F[7], sy, sz) * ihyz;
+            sec[q][a] = deriv2<D2, RAD>(F[q], st[a]) * ih2[a];
+    const D2 uxy = derivm<D2, RAD>(F[1], sx, sy) * ihxy, uyx = derivm<D2, RAD>(F[2], sx, sy) * ihxy;
+    const D2 uxz = derivm<D2, RAD>(F[1], sx, sz) * ihxz, uzx = derivm<D2, RAD>(F[3], sx, sz) * ihxz;
+    const D2 uyz = derivm<D2, RAD>(F[2], sy, sz) * ihyz, uzy = derivm<D2, RAD>(F[3], sy, sz) * ihyz;
+    const D2 axy = derivm<D2, RAD>(F[5], sx, sy) * ihxy, ayx = derivm<D2, RAD>(F[6], sx, sy) * ihxy;
+    const D2 axz = derivm<D2, RAD>(F[5], sx, sz) * ihxz, azx = derivm<D2, RAD>(F[7], sx, sz) * ihxz;
+    const D2 ayz = derivm<D2, RAD>(F[6], sy, sz) * ihyz, azy = derivm<D2, RAD>(F[7], sy, sz) * ihyz;
 
     d.lapl = Rt(sec[0][0] + sec[0][1] + sec[0][2]);
     d.laps = Rt(sec[4][0] + sec[4][1] + sec[4][2]);
@@ -105,27 +106,41 @@ __global__ __launch_bounds__(256) void k_rk3_direct(Grid g, Phys P, Box bx, int 
     }
 }
 
-}  // namespace
-
-hipError_t launch_rk3_direct(const Grid& g, const Phys& P, int precision, const Box& bx, int s,
-                             const void* f_in, void* f_out, void* w, void* comp, double dt,
-                             hipStream_t st)
+template <int RAD>
+void launch_order(const Grid& g, const Phys& P, int precision, const Box& bx, int s,
+                  const void* f_in, void* f_out, void* w, void* comp, double dt, hipStream_t st)
 {
     dim3 block(64, 4, 1);
     dim3 grid((bx.x1 - bx.x0 + 63) / 64, (bx.y1 - bx.y0 + 3) / 4, bx.z1 - bx.z0);
     switch (precision) {
     case MHD_F64:
-        hipLaunchKernelGGL(k_rk3_direct<MHD_F64>, grid, block, 0, st, g, P, bx, s,
+        hipLaunchKernelGGL((k_rk3_direct<MHD_F64, RAD>), grid, block, 0, st, g, P, bx, s,
                            (const double*)f_in, (double*)f_out, (double*)w, (double*)comp, dt);
         break;
     case MHD_F32C:
-        hipLaunchKernelGGL(k_rk3_direct<MHD_F32C>, grid, block, 0, st, g, P, bx, s,
+        hipLaunchKernelGGL((k_rk3_direct<MHD_F32C, RAD>), grid, block, 0, st, g, P, bx, s,
                            (const float*)f_in, (float*)f_out, (float*)w, (float*)comp, dt);
         break;
     default:
-        hipLaunchKernelGGL(k_rk3_direct<MHD_F32>, grid, block, 0, st, g, P, bx, s,
+        hipLaunchKernelGGL((k_rk3_direct<MHD_F32, RAD>), grid, block, 0, st, g, P, bx, s,
                            (const float*)f_in, (float*)f_out, (float*)w, (float*)nullptr, dt);
         break;
+    }
+}
+
+}  // namespace
+
+// The stencil radius is the grid's halo width g.r (1..4).
+hipError_t launch_rk3_direct(const Grid& g, const Phys& P, int precision, const Box& bx, int s,
+                             const void* f_in, void* f_out, void* w, void* comp, double dt,
+                             hipStream_t st)
+{
+    switch (g.r) {
+    case 1: launch_order<1>(g, P, precision, bx, s, f_in, f_out, w, comp, dt, st); break;
+    case 2: launch_order<2>(g, P, precision, bx, s, f_in, f_out, w, comp, dt, st); break;
+    case 3: launch_order<3>(g, P, precision, bx, s, f_in, f_out, w, comp, dt, st); break;
+    case 4: launch_order<4>(g, P, precision, bx, s, f_in, f_out, w, comp, dt, st); break;
+    default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

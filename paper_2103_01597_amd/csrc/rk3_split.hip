@@ -36,6 +36,7 @@ namespace {
 #ifndef MHD_SPLIT_TX
 #define MHD_SPLIT_TX 32
 #endif
+constexpr int R = 3;  // this kernel is built for the sixth-order stencil only
 constexpr int TX = MHD_SPLIT_TX, TY = 256 / MHD_SPLIT_TX, NC = TX * TY;  // cells per tile plane
 constexpr int NTH = 2 * NC;                    // threads: two groups of NC
 constexpr int HX = TX + 2 * R, HY = TY + 2 * R, PLANE = HX * HY;  // 38 x 14 = 532

@@ -42,11 +42,16 @@ namespace {
 #define MHD_TILED_TX 32
 #endif
 constexpr int TX = MHD_TILED_TX, TY = 256 / MHD_TILED_TX, NT = TX * TY;
-constexpr int HX = TX + 2 * R, HY = TY + 2 * R, PLANE = HX * HY;  // 38 x 14 = 532
-constexpr int SLOT = NQ * PLANE;
-constexpr int NSLOT = 4;
-constexpr int FULL = PLANE / NT;     // plane elements every thread loads
-constexpr int EXTRA = PLANE % NT;    // threads that load one more element
+// Per stencil radius RAD: the halo'd tile plane (38 x 14 = 532 cells at
+// RAD = 3) and the LDS ring of RAD + 1 such planes of all 8 fields.
+template <int RAD>
+struct Ring {
+    static constexpr int HX = TX + 2 * RAD, HY = TY + 2 * RAD, PLANE = HX * HY;
+    static constexpr int SLOT = NQ * PLANE;
+    static constexpr int NSLOT = RAD + 1;
+    static constexpr int FULL = PLANE / NT;   // plane elements every thread loads
+    static constexpr int EXTRA = PLANE % NT;  // threads that load one more element
+};
 // Scheduling fences between the per-field derivative phases (bit i: after
 // phase i) bound the live ranges of the LDS reads the scheduler may hoist.
 #ifndef MHD_TILED_FENCES
@@ -57,8 +62,8 @@ constexpr unsigned FENCE_MASK = MHD_TILED_FENCES;
 #define MHD_TILED_F32_BLOCKS 1
 #endif
 
-template <typename T>
-constexpr size_t lds_bytes() { return sizeof(T) * NSLOT * SLOT; }
+template <typename T, int RAD>
+constexpr size_t lds_bytes() { return sizeof(T) * Ring<RAD>::NSLOT * Ring<RAD>::SLOT; }
 
 struct TileMap {
     int ntx, nty;   // tiles per axis
@@ -68,11 +73,11 @@ struct TileMap {
 
 // Per-axis scale factors of the integer-weight stencils.
 struct Scales {
-    double d1[3];   // 1/(60 h_a)
-    double d2[3];   // 1/(180 h_a^2)
-    double mxy;     // 1/(720 h_x h_y)
-    double wxz[3];  // {270, -27, 2}/(720 h_x h_z)
-    double wyz[3];  // {270, -27, 2}/(720 h_y h_z)
+    double d1[3];   // 1/(DEN1 h_a)
+    double d2[3];   // 1/(DEN2 h_a^2)
+    double mxy;        // 1/(4 DEN2 h_x h_y)
+    double wxz[RMAX];  // W2(r, m)/(4 DEN2 h_x h_z), m = 1..r
+    double wyz[RMAX];  // W2(r, m)/(4 DEN2 h_y h_z)
 };
 
 constexpr int NO_TILE = -1;
@@ -127,7 +132,7 @@ __device__ __forceinline__ int tile_of_block(int b, const TileMap& m)
 template <int PREC>
 constexpr int blocks_per_cu() { return PREC == MHD_F64 ? 1 : MHD_TILED_F32_BLOCKS; }
 
-template <int PREC>
+template <int PREC, int RAD>
 __global__ __launch_bounds__(NT, blocks_per_cu<PREC>()) void k_rk3_tiled(Grid g, Phys P, Scales sc, TileMap map, int s,
                                                      const typename Prec<PREC>::T* __restrict__ fin,
                                                      typename Prec<PREC>::T* __restrict__ fout,
@@ -141,6 +146,8 @@ __global__ __launch_bounds__(NT, blocks_per_cu<PREC>()) void k_rk3_tiled(Grid g,
     using T = typename Prec<PREC>::T;
     using Rt = typename Prec<PREC>::Rt;
     using D2 = typename Prec<PREC>::D2;
+    constexpr int HX = Ring<RAD>::HX, PLANE = Ring<RAD>::PLANE, SLOT = Ring<RAD>::SLOT;
+    constexpr int NSLOT = Ring<RAD>::NSLOT, FULL = Ring<RAD>::FULL, EXTRA = Ring<RAD>::EXTRA;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* __restrict__ lds = reinterpret_cast<T*>(smem_raw);
 
@@ -179,8 +186,8 @@ __global__ __launch_bounds__(NT, blocks_per_cu<PREC>()) void k_rk3_tiled(Grid g,
     }
 
     T pre[NQ][NLOAD];
-    auto load_plane = [&](int t) {  // t: interior plane index, -3 .. nz+2
-        const unsigned zo = (unsigned)((t + R) * g.mxy);
+    auto load_plane = [&](int t) {  // t: interior plane index, -RAD .. nz+RAD-1
+        const unsigned zo = (unsigned)((t + RAD) * g.mxy);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             const T* f = field_ptr(fin, q);
@@ -211,41 +218,43 @@ __global__ __launch_bounds__(NT, blocks_per_cu<PREC>()) void k_rk3_tiled(Grid g,
     // V(slot, q, dy, dx): field q of the ring slot at offset (dx, dy) from the
     // thread's cell.  Addressed from the cell's stencil corner so that every
     // offset is a non-negative constant the LDS instructions take as an immediate.
-    const int corner = ly * HX + lx;  // cell (x - R, y - R) within a plane
+    const int corner = ly * HX + lx;  // cell (x - RAD, y - RAD) within a plane
     auto V = [&](int slot, int q, int dy, int dx) -> T {
-        return lds[(slot * SLOT + corner) + (q * PLANE + (dy + R) * HX + (dx + R))];
+        return lds[(slot * SLOT + corner) + (q * PLANE + (dy + RAD) * HX + (dx + RAD))];
     };
 
-    // ---- z state: own-column history (planes t-3, t-2, t-1) and the past
-    // halves of the six xz/yz mixed combinations for outputs t+1, t+2, t+3:
+    // ---- z state: own-column history (planes t-RAD .. t-1) and the past
+    // halves of the six xz/yz mixed combinations for outputs t+1 .. t+RAD:
     //   0: Dxz uz   1: Dyz uz   2: Dxz ux + Dyz uy
     //   3: Dxz Az   4: Dyz Az   5: Dxz Ax + Dyz Ay
-    T hist[3][NQ];
-    D2 past[6][3];
+    T hist[RAD][NQ];
+    D2 past[6][RAD];
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < RAD; ++k)
 #pragma unroll
         for (int q = 0; q < NQ; ++q) hist[k][q] = T(0);
 #pragma unroll
     for (int c = 0; c < 6; ++c)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) past[c][k] = D2(0);
+        for (int k = 0; k < RAD; ++k) past[c][k] = D2(0);
     // wold, cc: the 2N register and compensation of the next plane, fetched a
     // plane ahead; wnew, fnew, cnew: this plane's results
     T wold[NQ] = {}, wnew[NQ] = {}, fnew[NQ] = {}, cc[NQ] = {}, cnew[NQ] = {};
 
     auto cell_index = [&](int t) { return g.interior + t * g.mxy + (y0 + ly) * g.mx + (x0 + lx); };
 
-    constexpr int SOFS = 8;  // keeps (t + SOFS) non-negative for slot arithmetic
-    load_plane(bz0 - 3);
+    constexpr int SOFS = 4 * NSLOT;  // keeps (t + SOFS) non-negative for slot arithmetic
+    load_plane(bz0 - RAD);
     // u: plane index relative to the box start, so that the warm-up tests
-    // below compare against constants
-    for (int u = -7; u < bz1 - bz0; ++u) {
+    // below compare against constants.  Iterations u < -RAD only fill the
+    // ring; u in [-RAD, 0) are warm-up planes.
+    for (int u = -(2 * RAD + 1); u < bz1 - bz0; ++u) {
         const int t = bz0 + u;
-        if (u >= -3) {
-            const int s0 = (t + SOFS) & 3, s1 = (t + 1 + SOFS) & 3, s2 = (t + 2 + SOFS) & 3,
-                      s3 = (t + 3 + SOFS) & 3;
-            const int sl[4] = {s0, s1, s2, s3};
+        if (u >= -RAD) {
+            int sl[RAD + 1];  // ring slots of planes t .. t+RAD
+#pragma unroll
+            for (int k = 0; k <= RAD; ++k) sl[k] = (t + k + SOFS) % NSLOT;
+            const int s0 = sl[0];
             // warm-up planes (t < z0) run the whole computation too (branch-free
             // code schedules better); only their z state is kept
 
@@ -261,56 +270,67 @@ __global__ __launch_bounds__(NT, blocks_per_cu<PREC>()) void k_rk3_tiled(Grid g,
                     return dir == 0 ? Rt(V(s0, q, 0, m)) - Rt(V(s0, q, 0, -m))
                                     : Rt(V(s0, q, m, 0)) - Rt(V(s0, q, -m, 0));
                 };
-                return (Rt(45) * g1(1) - Rt(9) * g1(2) + g1(3)) * Rt(sc.d1[dir]);
+                Rt acc = Rt(W1(RAD, 1)) * g1(1);
+#pragma unroll
+                for (int m = 2; m <= RAD; ++m) acc += Rt(W1(RAD, m)) * g1(m);
+                return acc * Rt(sc.d1[dir]);
             };
-            auto col = [&](int q, int k) -> T {  // own column, plane t+k, k = -3..3
-                return k < 0 ? hist[k + 3][q] : V(sl[k], q, 0, 0);
+            auto col = [&](int q, int k) -> T {  // own column, plane t+k, k = -RAD..RAD
+                return k < 0 ? hist[k + RAD][q] : V(sl[k], q, 0, 0);
             };
             auto dz1 = [&](int q) -> Rt {
-                return (Rt(45) * (Rt(col(q, 1)) - Rt(col(q, -1))) -
-                        Rt(9) * (Rt(col(q, 2)) - Rt(col(q, -2))) +
-                        (Rt(col(q, 3)) - Rt(col(q, -3)))) * Rt(sc.d1[2]);
+                Rt acc = Rt(W1(RAD, 1)) * (Rt(col(q, 1)) - Rt(col(q, -1)));
+#pragma unroll
+                for (int m = 2; m <= RAD; ++m) acc += Rt(W1(RAD, m)) * (Rt(col(q, m)) - Rt(col(q, -m)));
+                return acc * Rt(sc.d1[2]);
             };
             // pure second derivatives along x, y, z
             auto second = [&](int q, D2& xx, D2& yy, D2& zz) {
-                const D2 f0 = D2(-490) * D2(V(s0, q, 0, 0));
-                xx = (D2(270) * sum2(q, 0, 1) - D2(27) * sum2(q, 0, 2) + D2(2) * sum2(q, 0, 3) + f0) *
-                     D2(sc.d2[0]);
-                yy = (D2(270) * sum2(q, 1, 1) - D2(27) * sum2(q, 1, 2) + D2(2) * sum2(q, 1, 3) + f0) *
-                     D2(sc.d2[1]);
-                zz = (D2(270) * (D2(col(q, 1)) + D2(col(q, -1))) -
-                      D2(27) * (D2(col(q, 2)) + D2(col(q, -2))) +
-                      D2(2) * (D2(col(q, 3)) + D2(col(q, -3))) + f0) * D2(sc.d2[2]);
+                const D2 f0 = D2(W2(RAD, 0)) * D2(V(s0, q, 0, 0));
+                D2 ax = D2(W2(RAD, 1)) * sum2(q, 0, 1), ay = D2(W2(RAD, 1)) * sum2(q, 1, 1);
+                D2 az = D2(W2(RAD, 1)) * (D2(col(q, 1)) + D2(col(q, -1)));
+#pragma unroll
+                for (int m = 2; m <= RAD; ++m) {
+                    ax += D2(W2(RAD, m)) * sum2(q, 0, m);
+                    ay += D2(W2(RAD, m)) * sum2(q, 1, m);
+                    az += D2(W2(RAD, m)) * (D2(col(q, m)) + D2(col(q, -m)));
+                }
+                xx = (ax + f0) * D2(sc.d2[0]);
+                yy = (ay + f0) * D2(sc.d2[1]);
+                zz = (az + f0) * D2(sc.d2[2]);
             };
             auto dxy = [&](int q) -> D2 {
                 auto e = [&](int m) {
                     return (D2(V(s0, q, m, m)) + D2(V(s0, q, -m, -m))) -
                            (D2(V(s0, q, -m, m)) + D2(V(s0, q, m, -m)));
                 };
-                return (D2(270) * e(1) - D2(27) * e(2) + D2(2) * e(3)) * D2(sc.mxy);
+                D2 acc = D2(W2(RAD, 1)) * e(1);
+#pragma unroll
+                for (int m = 2; m <= RAD; ++m) acc += D2(W2(RAD, m)) * e(m);
+                return acc * D2(sc.mxy);
             };
             // xz (dir 0) / yz (dir 1) mixed derivative of field q for combination
-            // cb: the future half from ring planes t+1..t+3 minus the carried past
-            // half (when `first_of_combo`); then the combination's carried state
-            // is advanced by plane t's own differences.
+            // cb: the future half from ring planes t+1..t+RAD minus the carried
+            // past half (when `first_of_combo`); then the combination's carried
+            // state is advanced by plane t's own differences: past[cb][k] holds
+            // the past half of output plane t+1+k.
             auto mixed = [&](int q, int dir, int cb, bool first_of_combo) -> D2 {
                 const double* wm = dir == 0 ? sc.wxz : sc.wyz;
                 auto dd = [&](int slot, int m) {
                     return dir == 0 ? D2(V(slot, q, 0, m)) - D2(V(slot, q, 0, -m))
                                     : D2(V(slot, q, m, 0)) - D2(V(slot, q, -m, 0));
                 };
-                D2 res = D2(wm[0]) * dd(s1, 1) + D2(wm[1]) * dd(s2, 2) + D2(wm[2]) * dd(s3, 3);
+                D2 res = D2(wm[0]) * dd(sl[1], 1);
+#pragma unroll
+                for (int m = 2; m <= RAD; ++m) res += D2(wm[m - 1]) * dd(sl[m], m);
                 if (first_of_combo) res -= past[cb][0];
-                const D2 c1 = D2(wm[0]) * dd(s0, 1), c2 = D2(wm[1]) * dd(s0, 2),
-                         c3 = D2(wm[2]) * dd(s0, 3);
-                if (first_of_combo) {
-                    past[cb][0] = past[cb][1] + c1;
-                    past[cb][1] = past[cb][2] + c2;
-                    past[cb][2] = c3;
-                } else {
-                    past[cb][0] += c1;
-                    past[cb][1] += c2;
-                    past[cb][2] += c3;
+#pragma unroll
+                for (int m = 1; m <= RAD; ++m) {
+                    const D2 c = D2(wm[m - 1]) * dd(s0, m);
+                    if (first_of_combo)
+                        past[cb][m - 1] = m < RAD ? past[cb][m < RAD ? m : 0] + c : c;
+                    else
+                        past[cb][m - 1] += c;
                 }
                 return res;
             };
@@ -433,20 +453,20 @@ __global__ __launch_bounds__(NT, blocks_per_cu<PREC>()) void k_rk3_tiled(Grid g,
             // ---- advance the own-column history past plane t
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
-                hist[0][q] = hist[1][q];
-                hist[1][q] = hist[2][q];
-                hist[2][q] = V(s0, q, 0, 0);
+#pragma unroll
+                for (int k = 0; k + 1 < RAD; ++k) hist[k][q] = hist[k + 1][q];
+                hist[RAD - 1][q] = V(s0, q, 0, 0);
             }
         }
 
-        // ---- plane t+4 replaces plane t in the ring; then plane t+5 and the
+        // ---- plane t+RAD+1 replaces plane t in the ring; then plane t+RAD+2 and the
         // next plane's register values are fetched, and only then do this
         // plane's results go out.  The vector-memory counter covers loads and
         // stores alike in issue order, so with the loads first the next
         // plane's waits for them do not also wait for these stores.
         __syncthreads();  // every read of plane t is done
-        store_plane((t + 4 + SOFS) & 3);
-        if (t + 5 <= bz1 + 2) load_plane(t + 5);
+        store_plane((t + RAD + 1 + SOFS) % NSLOT);
+        if (t + RAD + 2 <= bz1 + RAD - 1) load_plane(t + RAD + 2);
         if (active && u + 1 >= 0 && t + 1 < bz1) {
             const unsigned c = (unsigned)cell_index(t + 1);
             if (s > 0) {
@@ -467,23 +487,23 @@ __global__ __launch_bounds__(NT, blocks_per_cu<PREC>()) void k_rk3_tiled(Grid g,
                 if constexpr (PREC == MHD_F32C) *at(field_ptr(comp, q), c) = cnew[q];
             }
         }
-        __syncthreads();  // plane t+4 visible to every wave
+        __syncthreads();  // plane t+RAD+1 visible to every wave
     }
 }
 
-template <int PREC>
+template <int PREC, int RAD>
 hipError_t launch_one(const Grid& g, const Phys& P, const Box& bx, int s, const void* f_in,
                       void* f_out, void* w, void* comp, double dt, hipStream_t st)
 {
     using T = typename Prec<PREC>::T;
     static int round = -1;  // resident workgroups per round on this device
-    const size_t lds = lds_bytes<T>();
+    constexpr size_t lds = lds_bytes<T, RAD>();
     if (round < 0) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_rk3_tiled<PREC>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_rk3_tiled<PREC, RAD>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         int per_cu = 0, dev = 0, cus = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rk3_tiled<PREC>, NT, lds);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rk3_tiled<PREC, RAD>, NT, lds);
         if (e != hipSuccess) return e;
         e = hipGetDevice(&dev);
         if (e != hipSuccess) return e;
@@ -496,36 +516,56 @@ hipError_t launch_one(const Grid& g, const Phys& P, const Box& bx, int s, const 
     m.nty = (bx.y1 - bx.y0 + TY - 1) / TY;
     m.round = round;
     z_chunks(m, bx.z1 - bx.z0);
-    Scales sc;
+    Scales sc{};
     for (int a = 0; a < 3; ++a) {
-        sc.d1[a] = P.inv_h[a] / 60.0;
-        sc.d2[a] = P.inv_h[a] * P.inv_h[a] / 180.0;
+        sc.d1[a] = P.inv_h[a] / DEN1(RAD);
+        sc.d2[a] = P.inv_h[a] * P.inv_h[a] / DEN2(RAD);
     }
-    sc.mxy = P.inv_h[0] * P.inv_h[1] / 720.0;
-    const double wm[3] = {270.0, -27.0, 2.0};
-    for (int m3 = 0; m3 < 3; ++m3) {
-        sc.wxz[m3] = wm[m3] * P.inv_h[0] * P.inv_h[2] / 720.0;
-        sc.wyz[m3] = wm[m3] * P.inv_h[1] * P.inv_h[2] / 720.0;
+    sc.mxy = P.inv_h[0] * P.inv_h[1] / (4.0 * DEN2(RAD));
+    for (int k = 1; k <= RAD; ++k) {
+        sc.wxz[k - 1] = W2(RAD, k) * P.inv_h[0] * P.inv_h[2] / (4.0 * DEN2(RAD));
+        sc.wyz[k - 1] = W2(RAD, k) * P.inv_h[1] * P.inv_h[2] / (4.0 * DEN2(RAD));
     }
     const int tiles = m.ntx * m.nty * m.nch;
     // with the XCD mapping the last round may name tiles past the end; those
     // workgroups exit at once
     const int blocks = (round > 0 && (round & 7) == 0) ? (tiles + round - 1) / round * round : tiles;
-    hipLaunchKernelGGL(k_rk3_tiled<PREC>, dim3(blocks), dim3(NT), lds, st, g, P, sc, m, s,
+    hipLaunchKernelGGL((k_rk3_tiled<PREC, RAD>), dim3(blocks), dim3(NT), lds, st, g, P, sc, m, s,
                        (const T*)f_in, (T*)f_out, (T*)w, (T*)comp, dt, bx);
     return hipGetLastError();
 }
 
+template <int RAD>
+hipError_t launch_order(const Grid& g, const Phys& P, int precision, const Box& bx, int s,
+                        const void* f_in, void* f_out, void* w, void* comp, double dt,
+                        hipStream_t st)
+{
+    switch (precision) {
+    case MHD_F64:
+        // the FP64 ring of RAD + 1 planes fits the 160 KB of LDS up to RAD = 3
+        if constexpr (lds_bytes<double, RAD>() <= 160 * 1024)
+            return launch_one<MHD_F64, RAD>(g, P, bx, s, f_in, f_out, w, nullptr, dt, st);
+        else
+            return hipErrorInvalidValue;
+    case MHD_F32C: return launch_one<MHD_F32C, RAD>(g, P, bx, s, f_in, f_out, w, comp, dt, st);
+    default: return launch_one<MHD_F32, RAD>(g, P, bx, s, f_in, f_out, w, nullptr, dt, st);
+    }
+}
+
 }  // namespace
 
+// The stencil radius is the grid's halo width g.r (1..4); FP64 at r = 4
+// is not built (its ring exceeds the LDS) and returns hipErrorInvalidValue.
 hipError_t launch_rk3_tiled(const Grid& g, const Phys& P, int precision, const Box& bx, int s,
                             const void* f_in, void* f_out, void* w, void* comp, double dt,
                             hipStream_t st)
 {
-    switch (precision) {
-    case MHD_F64: return launch_one<MHD_F64>(g, P, bx, s, f_in, f_out, w, nullptr, dt, st);
-    case MHD_F32C: return launch_one<MHD_F32C>(g, P, bx, s, f_in, f_out, w, comp, dt, st);
-    default: return launch_one<MHD_F32>(g, P, bx, s, f_in, f_out, w, nullptr, dt, st);
+    switch (g.r) {
+    case 1: return launch_order<1>(g, P, precision, bx, s, f_in, f_out, w, comp, dt, st);
+    case 2: return launch_order<2>(g, P, precision, bx, s, f_in, f_out, w, comp, dt, st);
+    case 3: return launch_order<3>(g, P, precision, bx, s, f_in, f_out, w, comp, dt, st);
+    case 4: return launch_order<4>(g, P, precision, bx, s, f_in, f_out, w, comp, dt, st);
+    default: return hipErrorInvalidValue;
     }
 }
 

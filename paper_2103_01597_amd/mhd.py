@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libmhd.so")
 
 F64, F32C, F32 = 0, 1, 2
 PRECISIONS = {"f64": F64, "f32c": F32C, "f32": F32}
-KERNELS = {"tiled": 0, "direct": 1, "split": 2}
+KERNELS = {"tiled": 0, "direct": 1, "split": 2, "auto": 3}
 RED_OPS = {"sum": 0, "sumsq": 1, "maxabs": 2, "min": 3, "max": 4, "sumexp": 5, "nonfinite": 6}
 FIELD_NAMES = ("lnrho", "ux", "uy", "uz", "ss", "ax", "ay", "az")
 STATUS = {0: "MHD_OK", 1: "MHD_ERR_INVALID", 2: "MHD_ERR_NO_DEVICE", 3: "MHD_ERR_DEVICE",
@@ -34,7 +34,7 @@ EXPORTS = ("mhd_config_default", "mhd_init", "mhd_finalize", "mhd_strerror",
 class Config(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("kernel", ctypes.c_int32),
-                ("reserved_", ctypes.c_int32),
+                ("order", ctypes.c_int32),
                 ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double),
                 ("cs0", ctypes.c_double), ("gamma", ctypes.c_double), ("cp", ctypes.c_double),
                 ("lnrho0", ctypes.c_double), ("mu0", ctypes.c_double), ("nu", ctypes.c_double),
@@ -44,7 +44,8 @@ class Config(ctypes.Structure):
 
 class Layout(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
-                ("mx", "my", "mz", "field_stride", "elem_size", "interior_offset", "total_elems")]
+                ("mx", "my", "mz", "field_stride", "elem_size", "interior_offset", "total_elems",
+                 "halo", "kernel")]
 
 
 class Box(ctypes.Structure):
@@ -118,13 +119,13 @@ class Solver:
     :meth:`grid_view` / :meth:`interior_view` for (8, mz, my, mx) views.
     """
 
-    def __init__(self, nx, ny, nz, precision="f64", kernel=None, **phys):
+    def __init__(self, nx, ny, nz, precision="f64", kernel=None, order=6, **phys):
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         cfg = Config()
         lib().mhd_config_default(ctypes.byref(cfg), nx, ny, nz, self.precision)
-        if kernel is not None:  # None: the library's default for the precision
+        cfg.order = int(order)
+        if kernel is not None:  # None: the library picks (MHD_KERNEL_AUTO)
             cfg.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
-        self.kernel = {v: k for k, v in KERNELS.items()}[cfg.kernel]
         for k, v in phys.items():
             if k == "bext":
                 cfg.bext = (ctypes.c_double * 3)(*[float(b) for b in v])
@@ -138,6 +139,9 @@ class Solver:
         _check("mhd_init", lib().mhd_init(ctypes.byref(cfg), ctypes.byref(self._ctx),
                                           ctypes.byref(self.layout)))
         self.n = (nx, ny, nz)
+        self.order = int(order)
+        self.r = int(self.layout.halo)
+        self.kernel = {v: k for k, v in KERNELS.items()}[int(self.layout.kernel)]
 
     def close(self):
         if self._ctx:
@@ -170,7 +174,8 @@ class Solver:
 
     def interior_view(self, buf):
         nx, ny, nz = self.n
-        return self.grid_view(buf)[:, 3:3 + nz, 3:3 + ny, 3:3 + nx]
+        r = self.r
+        return self.grid_view(buf)[:, r:r + nz, r:r + ny, r:r + nx]
 
     def upload(self, fields: np.ndarray, buf=None, fill_halo=True):
         """Copy an (8, nz, ny, nx) host array into the interior of a buffer

@@ -49,10 +49,10 @@ def test_strerror_and_defaults(L):
     assert (cfg.nx, cfg.ny, cfg.nz, cfg.precision) == (32, 16, 8, 1)
     assert cfg.gamma == 5.0 / 3.0 and cfg.nu == 5e-3 and cfg.eta == 5e-3 and cfg.K == 5e-3
     assert cfg.cs0 == 1.0 and cfg.cp == 1.0 and cfg.mu0 == 1.0 and cfg.zeta == 0.0
-    assert cfg.kernel == 0 and cfg.reserved_ == 0  # MHD_KERNEL_TILED for FP32C
+    assert cfg.kernel == 3 and cfg.order == 6  # MHD_KERNEL_AUTO, sixth order
     assert abs(cfg.lx - 6.283185307179586) < 1e-15 and list(cfg.bext) == [0.0, 0.0, 0.0]
     L.mhd_config_default(ctypes.byref(cfg), 8, 8, 8, mhd.F64)
-    assert cfg.kernel == 2  # MHD_KERNEL_SPLIT for FP64
+    assert cfg.kernel == 3 and cfg.order == 6
 
 
 def test_segment_count_of_null_context(L):
@@ -75,8 +75,11 @@ def _init(L, **kw):
 @pytest.mark.parametrize("bad", [dict(nx=0), dict(ny=-3), dict(precision=3), dict(precision=-1),
                                  dict(gamma=1.0), dict(cp=0.0), dict(mu0=0.0),
                                  dict(lx=float("nan")), dict(lz=-1.0), dict(nu=float("inf")),
-                                 dict(nx=3000, ny=3000, nz=3000), dict(kernel=3),
-                                 dict(reserved_=1)])
+                                 dict(nx=3000, ny=3000, nz=3000), dict(kernel=4),
+                                 dict(kernel=-1), dict(order=5), dict(order=0), dict(order=10),
+                                 dict(kernel=2, order=4), dict(kernel=0, order=8),
+                                 # 1023^3 FP32 cells fit a 4 GiB field, 1025^3 do not
+                                 dict(nx=1017, ny=1017, nz=1017, precision=2, order=8)])
 def test_init_rejects_invalid_config(L, bad):
     rc, ctx = _init(L, **bad)
     assert rc == 1
@@ -96,9 +99,12 @@ def test_null_arguments(L):
     L.mhd_finalize(None)
 
 
-def test_no_device_path(L):
+@pytest.mark.parametrize("ok", [dict(), dict(order=2), dict(order=8, kernel=1),
+                                dict(nx=1017, ny=1017, nz=1017, precision=2, order=6)])
+def test_no_device_path(L, ok):
+    """A valid configuration gets past validation to the device query."""
     if os.environ.get("HIP_VISIBLE_DEVICES") is None and os.path.exists("/dev/kfd"):
         pytest.skip("a GPU device node is present")
-    rc, ctx = _init(L)
+    rc, ctx = _init(L, **ok)
     assert rc == 2
     assert ctx.value is None

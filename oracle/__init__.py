@@ -48,7 +48,7 @@ class _Params(ctypes.Structure):
                 ("cs0", ctypes.c_double), ("gamma", ctypes.c_double), ("cp", ctypes.c_double),
                 ("lnrho0", ctypes.c_double), ("mu0", ctypes.c_double), ("nu", ctypes.c_double),
                 ("zeta", ctypes.c_double), ("eta", ctypes.c_double), ("K", ctypes.c_double),
-                ("bext", ctypes.c_double * 3)]
+                ("bext", ctypes.c_double * 3), ("heat", ctypes.c_double), ("cool", ctypes.c_double)]
 
 
 @dataclass
@@ -71,12 +71,14 @@ class Params:
     K: float = 5e-3
     bext: tuple = field(default=(0.0, 0.0, 0.0))
     order: int = 6  # stencil order k = 2r (Section 4)
+    heat: float = 0.0  # explicit heating H of Eq. B.3 (uniform)
+    cool: float = 0.0  # explicit cooling C of Eq. B.3 (uniform)
 
     def _c(self) -> _Params:
         p = _Params()
         p.radius = _radius(self.order)
         for name in ("nx", "ny", "nz", "lx", "ly", "lz", "cs0", "gamma", "cp", "lnrho0",
-                     "mu0", "nu", "zeta", "eta", "K"):
+                     "mu0", "nu", "zeta", "eta", "K", "heat", "cool"):
             setattr(p, name, getattr(self, name))
         p.bext = (ctypes.c_double * 3)(*[float(b) for b in self.bext])
         return p

@@ -34,9 +34,12 @@
  *   - RK3 coefficients: alpha = (0, -5/9, -153/128), beta = (1/3, 15/16, 8/15);
  *   - equation of state: ideal gas, cs^2 = cs0^2 exp(gamma s/cp
  *     + (gamma - 1)(ln rho - ln rho0)), and cp (gamma - 1) T = cs^2;
- *   - K constant, H = C = 0, so B.3 divided by rho T reads
+ *   - K constant; the explicit heating H and cooling C, for which the
+ *     paper gives no model, spatially uniform constants (0 by default), so
+ *     B.3 divided by rho T reads
  *     Ds/Dt = (K/rho)(lap lnT + |grad lnT|^2)
- *             + (1/T)(eta mu0 j.j / rho + 2 nu S:S + zeta (div u)^2);
+ *             + (1/T)((H - C)/rho + eta mu0 j.j / rho + 2 nu S:S
+ *                     + zeta (div u)^2);
  *   - j = (grad(div A) - lap A)/mu0, built from second derivatives (the
  *     radius-r form of mu0^-1 curl curl A);
  *   - B = curl A + B_ext with an optional uniform B_ext (zero by default);
@@ -60,6 +63,7 @@ typedef struct {
     double lx, ly, lz;
     double cs0, gamma, cp, lnrho0, mu0, nu, zeta, eta, K;
     double bext[3];
+    double heat, cool; /* H and C of Eq. B.3, uniform */
 } oracle_params;
 
 #define RMAX 4
@@ -283,8 +287,8 @@ static void rhs_cell(const oracle_params *p, const double *f, int64_t i, int64_t
             SS += S[a][b] * S[a][b];
     }
     const double conduction = (p->K / rho) * (laplnT + glnT2);
-    const double heating =
-        inv_T * (p->eta * p->mu0 * jj / rho + 2.0 * p->nu * SS + p->zeta * divu * divu);
+    const double heating = inv_T * ((p->heat - p->cool) / rho + p->eta * p->mu0 * jj / rho +
+                                    2.0 * p->nu * SS + p->zeta * divu * divu);
     out[Q_SS] = -u_dot_gss + conduction + heating;
 
     /* B.4: induction in the resistive gauge as printed. */

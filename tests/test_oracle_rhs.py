@@ -296,3 +296,44 @@ def test_linear_alfven_wave(oracle_mod):
     for q, vi in zip((2, 7), v):
         expect = eps * np.real(vi * mode)
         assert np.max(np.abs(out[q] - expect)) < 1e-4 * eps, q
+
+
+def _temperature(f, p):
+    """T from ln rho and s by the ideal-gas closure (Table B.2 reading)."""
+    cs2 = p.cs0 ** 2 * np.exp(p.gamma * f[4] / p.cp + (p.gamma - 1) * (f[0] - p.lnrho0))
+    return cs2 / (p.cp * (p.gamma - 1))
+
+
+def test_heating_minus_cooling_raises_internal_energy(oracle_mod):
+    """Eq. B.3 with uniform H and C on a uniform fluid at rest: every
+    derivative vanishes, rho T ds/dt = H - C, and with rho constant the
+    internal energy per volume rho c_v T (c_v = c_p/gamma) grows exactly
+    linearly at the rate H - C.  Integrated by the RK3 (error O(dt^4)
+    per step), the energy gain over 40 steps matches (H - C) t closely;
+    a sign slip, a missing 1/rho or 1/T, or a c_p in place of c_v fails."""
+    n = (6, 5, 4)
+    p = oracle_mod.Params(*n, **PHYS, heat=0.7, cool=0.2)
+    f = np.zeros((8, n[2], n[1], n[0]))
+    f[0] = 0.4   # ln rho
+    f[4] = 0.25  # s
+    f[5] = 0.3   # A uniform: B = curl A + B_ext = B_ext
+    dt, nsteps = 2e-3, 40
+    e0 = np.exp(f[0]) * (p.cp / p.gamma) * _temperature(f, p)
+    g = oracle_mod.step(f, dt, p, nsteps)
+    e1 = np.exp(g[0]) * (p.cp / p.gamma) * _temperature(g, p)
+    gain = (p.heat - p.cool) * dt * nsteps
+    assert np.allclose(e1 - e0, gain, rtol=1e-9, atol=0)
+    for q in (0, 1, 2, 3, 5, 6, 7):  # unchanged up to the rounding of the weight sums
+        assert np.allclose(g[q], f[q], rtol=0, atol=1e-14)
+
+
+def test_heating_cooling_enter_only_the_entropy(oracle_mod):
+    n = (9, 8, 7)
+    f = inputs.fourier_modes(n, 3, 0.2, seed=51)
+    p0 = oracle_mod.Params(*n, **PHYS)
+    p1 = oracle_mod.Params(*n, **PHYS, heat=0.35, cool=0.1)
+    d = oracle_mod.rhs(f, p1) - oracle_mod.rhs(f, p0)
+    for q in (0, 1, 2, 3, 5, 6, 7):
+        assert np.array_equal(d[q], np.zeros_like(d[q]))
+    rho_T = np.exp(f[0]) * _temperature(f, p0)
+    assert np.allclose(d[4], (p1.heat - p1.cool) / rho_T, rtol=1e-12, atol=0)

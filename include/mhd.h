@@ -73,11 +73,10 @@ enum mhd_reduce_op {
 
 /* ---------------------------------------------------------------- types */
 /* Which fused-substep kernel runs (same results up to rounding order).
- * Orders: DIRECT every order and precision; TILED every order except
- * order 8 in MHD_F64 (its LDS ring would exceed a CU's 160 KB); SPLIT
- * order 6 only.  AUTO: init picks the fastest available for the precision
- * and order (MHD_F64: SPLIT at order 6, TILED at orders 2 and 4, DIRECT at
- * order 8; otherwise TILED) and reports it in mhd_layout.kernel. */
+ * DIRECT and TILED serve every order and precision, SPLIT order 6 only.
+ * AUTO: init picks the fastest for the precision and order (SPLIT for
+ * MHD_F64 at order 6, TILED otherwise) and reports it in
+ * mhd_layout.kernel. */
 enum mhd_kernel {
     MHD_KERNEL_TILED = 0,  /* LDS-tiled z-marching kernel */
     MHD_KERNEL_DIRECT = 1, /* one thread per cell, stencil read from global memory */
@@ -99,6 +98,9 @@ typedef struct mhd_config {
      * diffusivity; radiative thermal conductivity (constant). */
     double cs0, gamma, cp, lnrho0, mu0, nu, zeta, eta, K;
     double bext[3];       /* uniform field added to curl A (zero by default) */
+    double heat, cool;    /* explicit heating H and cooling C of Eq. B.3, taken
+                             spatially uniform (the paper gives no model; 0 by
+                             default) */
 } mhd_config;
 
 /* Geometry of every buffer the caller allocates (f, w, comp), with a halo
@@ -130,7 +132,7 @@ typedef struct mhd_box {
 
 /* Fill *cfg with the defaults for an n = (nx, ny, nz) grid: l = 2*pi per
  * axis, cs0 = 1, gamma = 5/3, cp = 1, lnrho0 = 0, mu0 = 1,
- * nu = eta = 5e-3, zeta = 0, K = 5e-3, bext = 0, order = 6,
+ * nu = eta = 5e-3, zeta = 0, K = 5e-3, bext = 0, heat = cool = 0, order = 6,
  * kernel = MHD_KERNEL_AUTO.  Never fails. */
 void mhd_config_default(mhd_config *cfg, int32_t nx, int32_t ny, int32_t nz,
                         int32_t precision);

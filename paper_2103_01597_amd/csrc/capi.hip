@@ -62,8 +62,6 @@ int validate(const mhd_config* c)
     if (c->kernel < MHD_KERNEL_TILED || c->kernel > MHD_KERNEL_AUTO) return MHD_ERR_INVALID;
     if (c->order != 2 && c->order != 4 && c->order != 6 && c->order != 8) return MHD_ERR_INVALID;
     if (c->kernel == MHD_KERNEL_SPLIT && c->order != 6) return MHD_ERR_INVALID;
-    if (c->kernel == MHD_KERNEL_TILED && c->precision == MHD_F64 && c->order == 8)
-        return MHD_ERR_INVALID;
     if (!finite_pos(c->lx) || !finite_pos(c->ly) || !finite_pos(c->lz)) return MHD_ERR_INVALID;
     if (!isfinite(c->gamma) || c->gamma <= 1.0) return MHD_ERR_INVALID;
     if (!finite_pos(c->cp) || !isfinite(c->cs0) || !isfinite(c->lnrho0)) return MHD_ERR_INVALID;
@@ -73,6 +71,7 @@ int validate(const mhd_config* c)
         if (!isfinite(v)) return MHD_ERR_INVALID;
     for (double v : c->bext)
         if (!isfinite(v)) return MHD_ERR_INVALID;
+    if (!isfinite(c->heat) || !isfinite(c->cool)) return MHD_ERR_INVALID;
     // every padded field must be addressable with 32-bit offsets
     const int64_t mx = c->nx + c->order, my = c->ny + c->order, mz = c->nz + c->order;
     if (mx * my * mz > (int64_t)INT32_MAX - 4096) return MHD_ERR_INVALID;
@@ -293,12 +292,8 @@ int mhd_init(const mhd_config* cfg, mhd_ctx** out, mhd_layout* layout)
     // AUTO: the fastest kernel built for the precision and order (measured
     // at 512^3 and 256^3 on MI355X)
     if (cfg->kernel == MHD_KERNEL_AUTO) {
-        if (cfg->precision != MHD_F64)
-            ctx->cfg.kernel = MHD_KERNEL_TILED;
-        else
-            ctx->cfg.kernel = cfg->order == 6   ? MHD_KERNEL_SPLIT
-                              : cfg->order == 8 ? MHD_KERNEL_DIRECT
-                                                : MHD_KERNEL_TILED;
+        ctx->cfg.kernel = cfg->precision == MHD_F64 && cfg->order == 6 ? MHD_KERNEL_SPLIT
+                                                                       : MHD_KERNEL_TILED;
     }
     const int r = cfg->order / 2;
     mhd_layout& L = ctx->lay;
@@ -342,6 +337,7 @@ int mhd_init(const mhd_config* cfg, mhd_ctx** out, mhd_layout* layout)
     for (int a = 0; a < 3; ++a) P.bext[a] = cfg->bext[a];
     P.gamma_m1 = cfg->gamma - 1.0;
     P.cp_gm1 = cfg->cp * (cfg->gamma - 1.0);
+    P.hc = cfg->heat - cfg->cool;
 
     hipError_t e = hipMalloc(&ctx->red_partials, (REDUCE_BLOCKS + 1) * sizeof(double));
     ctx->seg = seg_table(ctx->grid);

@@ -40,6 +40,7 @@ struct Phys {
     double bext[3];
     double gamma_m1;       // gamma - 1
     double cp_gm1;         // cp*(gamma - 1)
+    double hc;             // H - C of Eq. B.3 (uniform heating minus cooling)
 };
 
 // Williamson 2N RK3 (the scheme cited in Section 4).
@@ -91,7 +92,7 @@ struct Derivs {
     Rt lapA[3], jmu[3];                // lap A and mu0*j = grad(div A) - lap A
 };
 
-// The right-hand side of Eqs. B.1-B.4 (H = C = 0, K constant) with the ideal
+// The right-hand side of Eqs. B.1-B.4 (uniform H and C, K constant) with the ideal
 // gas closure cs^2 = cs0^2 exp(gamma s/cp + (gamma-1)(lnrho - lnrho0)),
 // cp (gamma-1) T = cs^2; B = curl A + B_ext; S the traceless rate of shear.
 // It is assembled from four pieces so that a kernel may split the work
@@ -183,7 +184,8 @@ __device__ __forceinline__ void rhs_entropy_induction(const Derivs<Rt>& d, const
     const Rt jj = J[0] * J[0] + J[1] * J[1] + J[2] * J[2];
     const Rt udgs = u[0] * d.gs[0] + u[1] * d.gs[1] + u[2] * d.gs[2];
     out[0] = -udgs + Rt(P.K) * inv_rho * (laplnT + glnT2) +
-             inv_T * (eta * Rt(P.mu0) * jj * inv_rho + Rt(2) * nu * SS + zeta * divu * divu);
+             inv_T * ((Rt(P.hc) + eta * Rt(P.mu0) * jj) * inv_rho + Rt(2) * nu * SS +
+                      zeta * divu * divu);
 
     out[1] = u[1] * B[2] - u[2] * B[1] + eta * d.lapA[0];
     out[2] = u[2] * B[0] - u[0] * B[2] + eta * d.lapA[1];

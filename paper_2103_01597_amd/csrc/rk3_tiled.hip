@@ -1,33 +1,36 @@
-// Fused RHS + RK3 substep, LDS-tiled z-marching kernel for gfx950.
+// Fused RHS + RK3 substep, LDS-tiled z-marching kernel for gfx950, templated
+// on the stencil radius RAD = 1..4 (orders 2, 4, 6, 8 of Section 4).
 //
-// A workgroup of 256 threads owns a TX x TY = 32 x 8 column tile and marches
-// it through all nz planes, one interior cell per thread per plane.
+// A workgroup of 256 threads owns a TX x TY = 32 x 8 column tile (32 x 4 and
+// 128 threads for FP64 at RAD = 4) and marches it through the nz planes of
+// its box, one interior cell per thread per plane.
 //
-// On-chip data flow (FP64: 136 KB of LDS, one workgroup per CU):
-//   * LDS ring of 4 halo'd planes (t .. t+3) of all 8 fields, each plane the
-//     tile plus a 3-cell halo in x and y (38 x 14 cells).  Plane t+5 is
-//     fetched into registers while plane t is computed; plane t+4 (fetched
-//     one iteration earlier) replaces plane t in the ring at the end of the
-//     iteration, so the HBM stream overlaps the arithmetic.
+// On-chip data flow (sixth order, FP64: 136 KB of LDS, one workgroup per CU):
+//   * LDS ring of RAD + 1 halo'd planes (t .. t+RAD) of all 8 fields, each
+//     plane the tile plus a RAD-cell halo in x and y (38 x 14 cells at
+//     RAD = 3).  Plane t+RAD+2 is fetched into registers while plane t is
+//     computed; plane t+RAD+1 (fetched one iteration earlier) replaces plane
+//     t in the ring at the end of the iteration, so the HBM stream overlaps
+//     the arithmetic.
 //   * x/y first, second and xy-mixed derivatives of plane t read the
 //     plane-t slot (axis lines and planar diagonals of Eq. stencil-fd).
-//   * z derivatives use the thread's own column: planes t-3..t-1 from a
-//     3-deep register history, planes t..t+3 from the ring.
+//   * z derivatives use the thread's own column: planes t-RAD..t-1 from a
+//     RAD-deep register history, planes t..t+RAD from the ring.
 //   * The xz / yz mixed derivatives are differences of x (or y) differences
 //     taken on planes t +- m:  Dxz f(t) = sum_m w_m [d_m(t+m) - d_m(t-m)],
 //     d_m(p) = f(x+m, p) - f(x-m, p).  The t+m halves come from the ring;
 //     the t-m halves were formed when plane t-m was current (they are the
-//     same differences D_x needs there) and are carried in three running
+//     same differences D_x needs there) and are carried in RAD running
 //     accumulators per mixed combination.
 // Each input value is fetched from HBM once per tile plus the tile halo;
 // neighbouring tiles of one round run concurrently on the same XCD (see
 // tile_of_block), so halo fetches mostly hit its L2.
 //
-// Stencil weights are the integers of the sixth-order formulas (exact as
-// f64/f32 literals) with one scale factor per axis or plane:
-//   D_a f  = [45 d1 - 9 d2 + d3] / (60 h_a)
-//   D_aa f = [-490 f0 + 270 s1 - 27 s2 + 2 s3] / (180 h_a^2)
-//   D_ab f = [270 e1 - 27 e2 + 2 e3] / (720 h_a h_b)
+// Stencil weights are the integers W1, W2 of the central formulas of order
+// 2r (exact as f64/f32 literals) with one scale factor per axis or plane:
+//   D_a f  = [sum_m W1(m) d_m] / (DEN1 h_a)                 (45, -9, 1; 60 at r = 3)
+//   D_aa f = [W2(0) f0 + sum_m W2(m) s_m] / (DEN2 h_a^2)    (-490, 270, -27, 2; 180)
+//   D_ab f = [sum_m W2(m) e_m] / (4 DEN2 h_a h_b)
 // The right-hand side assembly and the 2N update are the same as in the
 // direct kernel (Appendix B; Williamson RK3).
 #include <type_traits>
@@ -41,11 +44,16 @@ namespace {
 #ifndef MHD_TILED_TX
 #define MHD_TILED_TX 32
 #endif
-constexpr int TX = MHD_TILED_TX, TY = 256 / MHD_TILED_TX, NT = TX * TY;
-// Per stencil radius RAD: the halo'd tile plane (38 x 14 = 532 cells at
-// RAD = 3) and the LDS ring of RAD + 1 such planes of all 8 fields.
-template <int RAD>
+constexpr int TX = MHD_TILED_TX;
+// Per precision and stencil radius RAD: the tile (TX x TY cells, one thread
+// each), the halo'd tile plane (38 x 14 = 532 cells at RAD = 3) and the LDS
+// ring of RAD + 1 such planes of all 8 fields.  FP64 at RAD = 4 uses a
+// 32 x 4 tile: its ring of five 40 x 12 planes (150 KB) fits the 160 KB of
+// LDS where five 40 x 16 planes (200 KB) would not.
+template <int PREC, int RAD>
 struct Ring {
+    static constexpr int TY = (PREC == MHD_F64 && RAD == 4) ? 128 / TX : 256 / TX;
+    static constexpr int NT = TX * TY;
     static constexpr int HX = TX + 2 * RAD, HY = TY + 2 * RAD, PLANE = HX * HY;
     static constexpr int SLOT = NQ * PLANE;
     static constexpr int NSLOT = RAD + 1;
@@ -62,8 +70,11 @@ constexpr unsigned FENCE_MASK = MHD_TILED_FENCES;
 #define MHD_TILED_F32_BLOCKS 1
 #endif
 
-template <typename T, int RAD>
-constexpr size_t lds_bytes() { return sizeof(T) * Ring<RAD>::NSLOT * Ring<RAD>::SLOT; }
+template <int PREC, int RAD>
+constexpr size_t lds_bytes()
+{
+    return sizeof(typename Prec<PREC>::T) * Ring<PREC, RAD>::NSLOT * Ring<PREC, RAD>::SLOT;
+}
 
 struct TileMap {
     int ntx, nty;   // tiles per axis
@@ -133,7 +144,7 @@ template <int PREC>
 constexpr int blocks_per_cu() { return PREC == MHD_F64 ? 1 : MHD_TILED_F32_BLOCKS; }
 
 template <int PREC, int RAD>
-__global__ __launch_bounds__(NT, blocks_per_cu<PREC>()) void k_rk3_tiled(Grid g, Phys P, Scales sc, TileMap map, int s,
+__global__ __launch_bounds__((Ring<PREC, RAD>::NT), blocks_per_cu<PREC>()) void k_rk3_tiled(Grid g, Phys P, Scales sc, TileMap map, int s,
                                                      const typename Prec<PREC>::T* __restrict__ fin,
                                                      typename Prec<PREC>::T* __restrict__ fout,
                                                      typename Prec<PREC>::T* __restrict__ w,
@@ -146,8 +157,9 @@ __global__ __launch_bounds__(NT, blocks_per_cu<PREC>()) void k_rk3_tiled(Grid g,
     using T = typename Prec<PREC>::T;
     using Rt = typename Prec<PREC>::Rt;
     using D2 = typename Prec<PREC>::D2;
-    constexpr int HX = Ring<RAD>::HX, PLANE = Ring<RAD>::PLANE, SLOT = Ring<RAD>::SLOT;
-    constexpr int NSLOT = Ring<RAD>::NSLOT, FULL = Ring<RAD>::FULL, EXTRA = Ring<RAD>::EXTRA;
+    using RG = Ring<PREC, RAD>;
+    constexpr int TY = RG::TY, NT = RG::NT, HX = RG::HX, PLANE = RG::PLANE, SLOT = RG::SLOT;
+    constexpr int NSLOT = RG::NSLOT, FULL = RG::FULL, EXTRA = RG::EXTRA;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* __restrict__ lds = reinterpret_cast<T*>(smem_raw);
 
@@ -497,7 +509,8 @@ hipError_t launch_one(const Grid& g, const Phys& P, const Box& bx, int s, const 
 {
     using T = typename Prec<PREC>::T;
     static int round = -1;  // resident workgroups per round on this device
-    constexpr size_t lds = lds_bytes<T, RAD>();
+    constexpr size_t lds = lds_bytes<PREC, RAD>();
+    constexpr int TY = Ring<PREC, RAD>::TY, NT = Ring<PREC, RAD>::NT;
     if (round < 0) {
         hipError_t e = hipFuncSetAttribute((const void*)k_rk3_tiled<PREC, RAD>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -542,11 +555,7 @@ hipError_t launch_order(const Grid& g, const Phys& P, int precision, const Box& 
 {
     switch (precision) {
     case MHD_F64:
-        // the FP64 ring of RAD + 1 planes fits the 160 KB of LDS up to RAD = 3
-        if constexpr (lds_bytes<double, RAD>() <= 160 * 1024)
-            return launch_one<MHD_F64, RAD>(g, P, bx, s, f_in, f_out, w, nullptr, dt, st);
-        else
-            return hipErrorInvalidValue;
+        return launch_one<MHD_F64, RAD>(g, P, bx, s, f_in, f_out, w, nullptr, dt, st);
     case MHD_F32C: return launch_one<MHD_F32C, RAD>(g, P, bx, s, f_in, f_out, w, comp, dt, st);
     default: return launch_one<MHD_F32, RAD>(g, P, bx, s, f_in, f_out, w, nullptr, dt, st);
     }
@@ -554,8 +563,7 @@ hipError_t launch_order(const Grid& g, const Phys& P, int precision, const Box& 
 
 }  // namespace
 
-// The stencil radius is the grid's halo width g.r (1..4); FP64 at r = 4
-// is not built (its ring exceeds the LDS) and returns hipErrorInvalidValue.
+// The stencil radius is the grid's halo width g.r (1..4).
 hipError_t launch_rk3_tiled(const Grid& g, const Phys& P, int precision, const Box& bx, int s,
                             const void* f_in, void* f_out, void* w, void* comp, double dt,
                             hipStream_t st)

@@ -39,7 +39,8 @@ class Config(ctypes.Structure):
                 ("cs0", ctypes.c_double), ("gamma", ctypes.c_double), ("cp", ctypes.c_double),
                 ("lnrho0", ctypes.c_double), ("mu0", ctypes.c_double), ("nu", ctypes.c_double),
                 ("zeta", ctypes.c_double), ("eta", ctypes.c_double), ("K", ctypes.c_double),
-                ("bext", ctypes.c_double * 3)]
+                ("bext", ctypes.c_double * 3), ("heat", ctypes.c_double),
+                ("cool", ctypes.c_double)]
 
 
 class Layout(ctypes.Structure):

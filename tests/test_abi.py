@@ -49,6 +49,7 @@ def test_strerror_and_defaults(L):
     assert (cfg.nx, cfg.ny, cfg.nz, cfg.precision) == (32, 16, 8, 1)
     assert cfg.gamma == 5.0 / 3.0 and cfg.nu == 5e-3 and cfg.eta == 5e-3 and cfg.K == 5e-3
     assert cfg.cs0 == 1.0 and cfg.cp == 1.0 and cfg.mu0 == 1.0 and cfg.zeta == 0.0
+    assert cfg.heat == 0.0 and cfg.cool == 0.0
     assert cfg.kernel == 3 and cfg.order == 6  # MHD_KERNEL_AUTO, sixth order
     assert abs(cfg.lx - 6.283185307179586) < 1e-15 and list(cfg.bext) == [0.0, 0.0, 0.0]
     L.mhd_config_default(ctypes.byref(cfg), 8, 8, 8, mhd.F64)
@@ -77,7 +78,8 @@ def _init(L, **kw):
                                  dict(lx=float("nan")), dict(lz=-1.0), dict(nu=float("inf")),
                                  dict(nx=3000, ny=3000, nz=3000), dict(kernel=4),
                                  dict(kernel=-1), dict(order=5), dict(order=0), dict(order=10),
-                                 dict(kernel=2, order=4), dict(kernel=0, order=8),
+                                 dict(kernel=2, order=4), dict(kernel=2, order=8),
+                                 dict(heat=float("inf")), dict(cool=float("nan")),
                                  # 1023^3 FP32 cells fit a 4 GiB field, 1025^3 do not
                                  dict(nx=1017, ny=1017, nz=1017, precision=2, order=8)])
 def test_init_rejects_invalid_config(L, bad):
@@ -100,6 +102,7 @@ def test_null_arguments(L):
 
 
 @pytest.mark.parametrize("ok", [dict(), dict(order=2), dict(order=8, kernel=1),
+                                dict(order=8, kernel=0),
                                 dict(nx=1017, ny=1017, nz=1017, precision=2, order=6)])
 def test_no_device_path(L, ok):
     """A valid configuration gets past validation to the device query."""

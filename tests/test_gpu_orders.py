@@ -85,7 +85,8 @@ def test_halo_fill_width_r(mhd, shape, prec, order):
     S.close()
 
 
-CASES = [(2, "tiled"), (2, "direct"), (4, "tiled"), (4, "direct"), (6, "tiled"), (8, "direct")]
+CASES = [(2, "tiled"), (2, "direct"), (4, "tiled"), (4, "direct"), (6, "tiled"), (8, "tiled"),
+         (8, "direct")]
 
 
 @pytest.mark.parametrize("order,kernel", CASES)
@@ -132,14 +133,13 @@ def test_orders_differ(mhd):
 
 
 def test_kernel_availability(mhd):
-    auto = {("f64", 2): "tiled", ("f64", 4): "tiled", ("f64", 6): "split", ("f64", 8): "direct",
+    auto = {("f64", 2): "tiled", ("f64", 4): "tiled", ("f64", 6): "split", ("f64", 8): "tiled",
             ("f32c", 2): "tiled", ("f32c", 8): "tiled", ("f32", 6): "tiled"}
     for (prec, order), kernel in auto.items():
         S = mhd.Solver(16, 16, 16, prec, order=order)
         assert S.kernel == kernel and S.r == order // 2
         S.close()
-    for prec, order, kernel in [("f64", 4, "split"), ("f32c", 8, "split"), ("f64", 8, "tiled"),
-                                ("f64", 2, "split")]:
+    for prec, order, kernel in [("f64", 4, "split"), ("f32c", 8, "split"), ("f64", 2, "split")]:
         with pytest.raises(mhd.MhdError):
             mhd.Solver(16, 16, 16, prec, kernel, order=order)
     with pytest.raises(mhd.MhdError):

@@ -61,54 +61,100 @@ constexpr int NTHR = 256;
 // ------------------------------------------------------------------ conv
 // MODE 0: hidden layer (z, GELU(z) as BF16); 1: output layer (FP32);
 // 2: data gradient (times GELU'(zprev), BF16).
+//
+// A block of CONV_THR threads owns a slab of CONV_CELLS / n full periodic
+// rows (CONV_CELLS cells per plane, 32 per wave) and marches it through a
+// chunk of zc planes.  LDS holds the weights and a ring of three planes of
+// the slab plus one periodic row on each side (channels last); plane p+2 is
+// fetched into registers while plane p is computed, so each input value is
+// read from memory (1 + 2 RY^-1)(1 + 2 zc^-1) times instead of once per
+// 3 x (rows + 2) neighbourhood of a small tile.
+constexpr int CONV_THR = 512;
+constexpr int CONV_CELLS = 256;  // cells per plane per block: 8 waves x 32
+
+template <int CIN>
+constexpr int conv_loads(int n)  // 16-byte vectors each thread moves per plane
+{
+    return ((CONV_CELLS / n + 2) * n * CIN / 8 + CONV_THR - 1) / CONV_THR;
+}
+
 template <int CIN, int MODE>
-__global__ __launch_bounds__(NTHR) void k_conv(const uint16_t* __restrict__ x,
-                                               const uint16_t* __restrict__ w,
-                                               const float* __restrict__ bias,
-                                               const uint16_t* __restrict__ zprev, int n, int logn,
-                                               int batch, int cout, uint16_t* __restrict__ out0,
-                                               uint16_t* __restrict__ out1, float* __restrict__ outf)
+__global__ __launch_bounds__(CONV_THR) void k_conv(const uint16_t* __restrict__ x,
+                                                   const uint16_t* __restrict__ w,
+                                                   const float* __restrict__ bias,
+                                                   const uint16_t* __restrict__ zprev, int n,
+                                                   int logn, int nch, int zc, int cout,
+                                                   uint16_t* __restrict__ out0,
+                                                   uint16_t* __restrict__ out1,
+                                                   float* __restrict__ outf)
 {
     extern __shared__ __align__(16) uint16_t sm[];
-    const int R = TILE >> logn;              // full rows per tile
+    const int RY = CONV_CELLS >> logn;       // rows per slab
+    const int slot = (RY + 2) * n * CIN;     // elements per ring plane
+    const int nv = slot / 8;                 // 16-byte vectors per ring plane
     uint16_t* lw = sm;                       // [32][27][CIN]
-    uint16_t* lx = sm + 32 * 27 * CIN;       // [3][R+2][n][CIN]
-    const int n3 = n * n * n, tiles_per = n3 / TILE, tiles = tiles_per * batch;
+    uint16_t* lx = sm + 32 * 27 * CIN;       // [3][RY+2][n][CIN]
+    const int slabs = n / RY;
+    const int col_id = blockIdx.x / nch, ch_id = blockIdx.x - col_id * nch;
+    const int b = col_id / slabs, y0 = (col_id - b * slabs) * RY;
+    const int z0 = ch_id * zc, nz = min(zc, n - z0);
+    const size_t n3 = (size_t)n * n * n;
+    const uint16_t* xb = x + (size_t)b * n3 * CIN;
     const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63, h = l >> 5, col = l & 31;
 
-    for (int i = tid; i < 32 * 27 * CIN / 8; i += NTHR)
+    for (int i = tid; i < 32 * 27 * CIN / 8; i += CONV_THR)
         reinterpret_cast<u16x8*>(lw)[i] = reinterpret_cast<const u16x8*>(w)[i];
 
-    for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
-        const int b = tile / tiles_per, c0 = (tile - b * tiles_per) * TILE;
-        const int k = c0 >> (2 * logn), j0 = (c0 >> logn) & (n - 1);
-        const uint16_t* xb = x + (size_t)b * n3 * CIN;
-        __syncthreads();  // previous tile's reads of lx are done (and lw is staged)
-        const int vecs = 3 * (R + 2) * n * CIN / 8;
-        for (int i = tid; i < vecs; i += NTHR) {
-            const int e = i * 8;                  // element index in lx
-            const int cell = e / CIN, ch = e - cell * CIN;
-            const int xx = cell & (n - 1), rp = cell >> logn;
-            const int r = rp % (R + 2), p = rp / (R + 2);
-            const int zz = (k - 1 + p + n) & (n - 1), yy = (j0 - 1 + r + n) & (n - 1);
-            const int src = (((zz << logn) + yy) << logn) + xx;
-            reinterpret_cast<u16x8*>(lx)[i] =
-                *reinterpret_cast<const u16x8*>(xb + (size_t)src * CIN + ch);
+    // ---- plane loads: vector i of ring plane z = rows y0-1 .. y0+RY (periodic)
+    constexpr int NL = conv_loads<CIN>(16) > conv_loads<CIN>(64) ? conv_loads<CIN>(16)
+                                                                    : conv_loads<CIN>(64);
+    u16x8 pre[NL];
+    auto load = [&](int z) {
+        const int zz = (z + n) & (n - 1);
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int i = tid + k * CONV_THR;
+            if (i < nv) {
+                const int e = i * 8, cell = e / CIN, ch = e - cell * CIN;
+                const int xx = cell & (n - 1), r = cell >> logn;
+                const int yy = (y0 - 1 + r + n) & (n - 1);
+                const size_t src = ((size_t)((zz << logn) + yy) << logn) + xx;
+                pre[k] = *reinterpret_cast<const u16x8*>(xb + src * CIN + ch);
+            }
         }
-        __syncthreads();
+    };
+    auto store = [&](int sl) {
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int i = tid + k * CONV_THR;
+            if (i < nv) reinterpret_cast<u16x8*>(lx + sl * slot)[i] = pre[k];
+        }
+    };
+    load(z0 - 1);
+    store(0);
+    load(z0);
+    store(1);
+    load(z0 + 1);
 
-        const int m = 32 * wv + col;             // this lane's A-row cell within the tile
-        const int rr = m >> logn, xx = m & (n - 1);
+    const int m = 32 * wv + col;             // this lane's A-row cell within the slab plane
+    const int rr = m >> logn, xx = m & (n - 1);
+    for (int p = 0; p < nz; ++p) {
+        // ring slot q holds plane z0 - 1 + (p' mod 3) for the p' with p' = q (mod 3)
+        store((p + 2) % 3);  // plane z0+p+1 replaces plane z0+p-2
+        __syncthreads();
+        if (p + 1 < nz) load(z0 + p + 2);
+        const int sb[3] = {(p % 3) * (RY + 2), ((p + 1) % 3) * (RY + 2), ((p + 2) % 3) * (RY + 2)};
+
         floatx16 acc = {};
         if constexpr (CIN == 32) {
 #pragma unroll 3
             for (int t = 0; t < 27; ++t) {
-                const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-                const int s = ((dz + 1) * (R + 2) + rr + dy + 1) * n + ((xx + dx) & (n - 1));
+                const int dz = t / 9, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+                const int s = (sb[dz] + rr + dy + 1) * n + ((xx + dx) & (n - 1));
 #pragma unroll
-                for (int ch = 0; ch < 2; ++ch) {
-                    const bf16x8 a = frag(lx + s * 32 + 16 * ch + 8 * h);
-                    const bf16x8 bb = frag(lw + (col * 27 + t) * 32 + 16 * ch + 8 * h);
+                for (int c2 = 0; c2 < 2; ++c2) {
+                    const bf16x8 a = frag(lx + s * 32 + 16 * c2 + 8 * h);
+                    const bf16x8 bb = frag(lw + (col * 27 + t) * 32 + 16 * c2 + 8 * h);
                     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, acc, 0, 0, 0);
                 }
             }
@@ -118,8 +164,8 @@ __global__ __launch_bounds__(NTHR) void k_conv(const uint16_t* __restrict__ x,
                 const int t = 2 * u + h;
                 bf16x8 a = {}, bb = {};
                 if (t < 27) {
-                    const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-                    const int s = ((dz + 1) * (R + 2) + rr + dy + 1) * n + ((xx + dx) & (n - 1));
+                    const int dz = t / 9, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+                    const int s = (sb[dz] + rr + dy + 1) * n + ((xx + dx) & (n - 1));
                     a = frag(lx + s * 8);
                     bb = frag(lw + (col * 27 + t) * 8);
                 }
@@ -129,10 +175,11 @@ __global__ __launch_bounds__(NTHR) void k_conv(const uint16_t* __restrict__ x,
 
         if (col < cout) {
             const float bv = (MODE == 2) ? 0.0f : bias[col];
+            const size_t c0 = (size_t)b * n3 + ((size_t)(z0 + p) << (2 * logn)) + ((size_t)y0 << logn);
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int cl = 32 * wv + 8 * (r >> 2) + 4 * h + (r & 3);
-                const size_t o = ((size_t)b * n3 + c0 + cl) * cout + col;
+                const size_t o = (c0 + cl) * cout + col;
                 const float v = acc[r] + bv;
                 if constexpr (MODE == 0) {
                     out0[o] = f2bf(v);
@@ -144,6 +191,7 @@ __global__ __launch_bounds__(NTHR) void k_conv(const uint16_t* __restrict__ x,
                 }
             }
         }
+        __syncthreads();  // every read of plane z0+p-1 is done before it is replaced
     }
 }
 
@@ -493,28 +541,33 @@ bool conv_n_ok(int n) { return n == 16 || n == 32 || n == 64; }
 
 int status(hipError_t e) { return e == hipSuccess ? MHD_OK : MHD_ERR_DEVICE; }
 
-size_t conv_lds(int cin, int n) { return 2 * (32 * 27 * cin + 3 * (TILE / n + 2) * n * cin); }
 size_t wgrad_lds(int cin, int n) { return 2 * (cin * 3 * (TILE / n + 2) * n + 3 * 32 * TILE); }
+
+size_t conv_lds(int cin, int n) { return 2 * (32 * 27 * cin + 3 * (CONV_CELLS / n + 2) * n * cin); }
 
 template <int CIN, int MODE>
 hipError_t launch_conv(const uint16_t* x, const uint16_t* w, const float* bias, const uint16_t* zp,
                        int n, int batch, int cout, uint16_t* o0, uint16_t* o1, float* of,
                        hipStream_t st)
 {
-    const size_t lds = conv_lds(CIN, n);
     static bool attr = false;
     if (!attr) {
+        const int most = (int)(conv_lds(CIN, 16) > conv_lds(CIN, 64) ? conv_lds(CIN, 16)
+                                                                      : conv_lds(CIN, 64));
         hipError_t e = hipFuncSetAttribute((const void*)k_conv<CIN, MODE>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)conv_lds(CIN, 16) > (int)conv_lds(CIN, 64)
-                                               ? (int)conv_lds(CIN, 16) : (int)conv_lds(CIN, 64));
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, most);
         if (e != hipSuccess) return e;
         attr = true;
     }
-    const int tiles = n * n * n / TILE * batch;
-    const int grid = tiles < 1024 ? tiles : 1024;
-    hipLaunchKernelGGL((k_conv<CIN, MODE>), dim3(grid), dim3(NTHR), lds, st, x, w, bias, zp, n,
-                       ilog2(n), batch, cout, o0, o1, of);
+    // z chunks so that about 256 blocks (one per CU) march at once
+    const int columns = batch * (n / (CONV_CELLS / n));
+    int nch = (256 + columns - 1) / columns;
+    nch = nch < 1 ? 1 : nch > n / 4 ? n / 4 : nch;
+    const int zc = (n + nch - 1) / nch;
+    nch = (n + zc - 1) / zc;
+    hipLaunchKernelGGL((k_conv<CIN, MODE>), dim3(columns * nch), dim3(CONV_THR),
+                       conv_lds(CIN, n), st, x, w, bias, zp, n, ilog2(n), nch, zc, cout, o0, o1,
+                       of);
     return hipGetLastError();
 }
 

@@ -1,17 +1,20 @@
 // Learned-closure kernels for gfx950 (declared in include/mhdnn.h).
 //
 // Periodic 3x3x3 convolutions run as implicit GEMMs on the BF16 matrix
-// cores (v_mfma_f32_32x32x16_bf16, FP32 accumulation):
+// cores (v_mfma_f32_32x32x16_bf16, FP32 accumulation).  A block of 512
+// threads owns a slab of 256 cells per plane (full periodic rows) and
+// marches it through a chunk of planes, with a three-plane ring of the slab
+// plus one row on each side in LDS and the next plane prefetched into
+// registers:
 //   * forward / data gradient: M = cells, N = output channels (padded to
-//     32), K = 27 taps x input channels.  A block stages its 128-cell tile's
-//     neighbourhood (3 planes x (R+2) full periodic rows, channels last) and
-//     the weights in LDS; each wave owns 32 cells.  An A fragment is 8
-//     consecutive channels of one shifted cell (one 16-byte LDS read); a B
-//     fragment is 8 consecutive input channels of one weight row.
+//     32), K = 27 taps x input channels; each wave owns 32 cells.  An A
+//     fragment is 8 consecutive channels of one shifted cell (one 16-byte
+//     LDS read); a B fragment is 8 consecutive input channels of one weight
+//     row.
 //   * weight gradient: M = output channels, N = input channels (or 4 taps x
 //     8 channels for 8-channel inputs), K = cells.  Over one full periodic
 //     x-row, sum_x dz(x) x(x + dx) = sum_q dz(q - dx) x(q), so the x shift is
-//     moved onto three pre-shifted LDS copies of the dz tile and every
+//     moved onto three pre-shifted LDS copies of the dz plane and every
 //     fragment is 8 consecutive, 16-byte aligned cells of one channel.
 //     Per-block partial sums go to a workspace that a second kernel reduces
 //     in a fixed order (deterministic).
@@ -55,7 +58,6 @@ __device__ __forceinline__ bf16x8 frag(const uint16_t* p)  // 16-byte aligned
     return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(p));
 }
 
-constexpr int TILE = 128;   // cells per conv tile
 constexpr int NTHR = 256;
 
 // ------------------------------------------------------------------ conv
@@ -71,6 +73,14 @@ constexpr int NTHR = 256;
 // 3 x (rows + 2) neighbourhood of a small tile.
 constexpr int CONV_THR = 512;
 constexpr int CONV_CELLS = 256;  // cells per plane per block: 8 waves x 32
+
+// LDS row pitches (elements), padded so that consecutive lanes' 16-byte
+// fragment reads start an odd number of 16-byte units apart (no bank
+// conflicts): per cell of the input ring, per output channel of the weights.
+template <int CIN>
+constexpr int conv_cp() { return CIN == 32 ? CIN + 8 : CIN; }
+template <int CIN>
+constexpr int conv_wrow() { return CIN == 32 ? 27 * CIN + 8 : 27 * CIN; }
 
 template <int CIN>
 constexpr int conv_loads(int n)  // 16-byte vectors each thread moves per plane
@@ -89,11 +99,12 @@ __global__ __launch_bounds__(CONV_THR) void k_conv(const uint16_t* __restrict__ 
                                                    float* __restrict__ outf)
 {
     extern __shared__ __align__(16) uint16_t sm[];
+    constexpr int CP = conv_cp<CIN>(), WROW = conv_wrow<CIN>();
     const int RY = CONV_CELLS >> logn;       // rows per slab
-    const int slot = (RY + 2) * n * CIN;     // elements per ring plane
-    const int nv = slot / 8;                 // 16-byte vectors per ring plane
-    uint16_t* lw = sm;                       // [32][27][CIN]
-    uint16_t* lx = sm + 32 * 27 * CIN;       // [3][RY+2][n][CIN]
+    const int slot = (RY + 2) * n * CP;      // elements per ring plane
+    const int nv = (RY + 2) * n * CIN / 8;   // 16-byte vectors per ring plane
+    uint16_t* lw = sm;                       // [32][WROW]: [27][CIN] per output channel
+    uint16_t* lx = sm + 32 * WROW;           // [3][RY+2][n][CP]
     const int slabs = n / RY;
     const int col_id = blockIdx.x / nch, ch_id = blockIdx.x - col_id * nch;
     const int b = col_id / slabs, y0 = (col_id - b * slabs) * RY;
@@ -102,8 +113,10 @@ __global__ __launch_bounds__(CONV_THR) void k_conv(const uint16_t* __restrict__ 
     const uint16_t* xb = x + (size_t)b * n3 * CIN;
     const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63, h = l >> 5, col = l & 31;
 
-    for (int i = tid; i < 32 * 27 * CIN / 8; i += CONV_THR)
-        reinterpret_cast<u16x8*>(lw)[i] = reinterpret_cast<const u16x8*>(w)[i];
+    for (int i = tid; i < 32 * 27 * CIN / 8; i += CONV_THR) {
+        const int o = i / (27 * CIN / 8), rem = i - o * (27 * CIN / 8);
+        *reinterpret_cast<u16x8*>(lw + o * WROW + rem * 8) = reinterpret_cast<const u16x8*>(w)[i];
+    }
 
     // ---- plane loads: vector i of ring plane z = rows y0-1 .. y0+RY (periodic)
     constexpr int NL = conv_loads<CIN>(16) > conv_loads<CIN>(64) ? conv_loads<CIN>(16)
@@ -127,7 +140,10 @@ __global__ __launch_bounds__(CONV_THR) void k_conv(const uint16_t* __restrict__ 
 #pragma unroll
         for (int k = 0; k < NL; ++k) {
             const int i = tid + k * CONV_THR;
-            if (i < nv) reinterpret_cast<u16x8*>(lx + sl * slot)[i] = pre[k];
+            if (i < nv) {
+                const int e = i * 8, cell = e / CIN, ch = e - cell * CIN;
+                *reinterpret_cast<u16x8*>(lx + sl * slot + cell * CP + ch) = pre[k];
+            }
         }
     };
     load(z0 - 1);
@@ -153,8 +169,8 @@ __global__ __launch_bounds__(CONV_THR) void k_conv(const uint16_t* __restrict__ 
                 const int s = (sb[dz] + rr + dy + 1) * n + ((xx + dx) & (n - 1));
 #pragma unroll
                 for (int c2 = 0; c2 < 2; ++c2) {
-                    const bf16x8 a = frag(lx + s * 32 + 16 * c2 + 8 * h);
-                    const bf16x8 bb = frag(lw + (col * 27 + t) * 32 + 16 * c2 + 8 * h);
+                    const bf16x8 a = frag(lx + s * CP + 16 * c2 + 8 * h);
+                    const bf16x8 bb = frag(lw + col * WROW + t * 32 + 16 * c2 + 8 * h);
                     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, acc, 0, 0, 0);
                 }
             }
@@ -166,8 +182,8 @@ __global__ __launch_bounds__(CONV_THR) void k_conv(const uint16_t* __restrict__ 
                 if (t < 27) {
                     const int dz = t / 9, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
                     const int s = (sb[dz] + rr + dy + 1) * n + ((xx + dx) & (n - 1));
-                    a = frag(lx + s * 8);
-                    bb = frag(lw + (col * 27 + t) * 8);
+                    a = frag(lx + s * CP);
+                    bb = frag(lw + col * WROW + t * 8);
                 }
                 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, acc, 0, 0, 0);
             }
@@ -196,111 +212,171 @@ __global__ __launch_bounds__(CONV_THR) void k_conv(const uint16_t* __restrict__ 
 }
 
 // --------------------------------------------------------------- wgrad
-constexpr int WG_TILES = 16;  // 128-cell tiles per wgrad block
-
+// Weight gradient dW[o][t][c] = sum over cells of dz[cell][o] x[cell + off(t)][c]
+// (and db[o] = sum dz[cell][o]) on the same slabs and z chunks as k_conv.
+// M = output channels, N = input channels (or 4 (dz, dy) taps x 8 channels
+// for 8-channel inputs), K = cells.  Over one full periodic x-row,
+// sum_x dz(x) x(x + dx) = sum_q dz(q - dx) x(q), so the x shift is moved onto
+// three pre-shifted LDS copies of the dz plane and every fragment is 8
+// consecutive, 16-byte aligned cells of one channel: x is kept channel-major
+// in a three-plane ring, dz channel-major for the current plane.  Each block
+// accumulates its chunk in registers and writes one partial sum per weight;
+// k_wgrad_reduce adds the partials in a fixed order (deterministic).
 template <int CIN, int COUT>
-__global__ __launch_bounds__(NTHR) void k_wgrad(const uint16_t* __restrict__ x,
-                                                const uint16_t* __restrict__ dz, int n, int logn,
-                                                int batch, float* __restrict__ ws,
-                                                float* __restrict__ wsb)
+__global__ __launch_bounds__(CONV_THR) void k_wgrad(const uint16_t* __restrict__ x,
+                                                    const uint16_t* __restrict__ dz, int n,
+                                                    int logn, int nch, int zc,
+                                                    float* __restrict__ ws,
+                                                    float* __restrict__ wsb)
 {
     extern __shared__ __align__(16) uint16_t sm[];
-    const int R = TILE >> logn;
-    uint16_t* xs = sm;                           // [CIN][3][R+2][n]
-    uint16_t* ds = sm + CIN * 3 * (R + 2) * n;   // [3 shifts][32][R][n]
-    __shared__ float bsum[NTHR];
-    const int n3 = n * n * n, tiles_per = n3 / TILE, tiles = tiles_per * batch;
+    const int RY = CONV_CELLS >> logn;
+    const int xplane = (RY + 2) * n;            // cells of one ring plane
+    // channel rows padded by 16 bytes: fragment reads of consecutive lanes
+    // (consecutive channels) start an odd number of 16-byte units apart
+    const int PS = xplane + 8;
+    constexpr int DS = CONV_CELLS + 8;
+    uint16_t* xs = sm;                          // [CIN][3][PS]: rows [RY+2][n]
+    uint16_t* ds = sm + CIN * 3 * PS;           // [3 shifts][32][DS]: rows [RY][n]
+    float* bsum = reinterpret_cast<float*>(ds + 3 * 32 * DS);  // [CONV_THR][8]
+    const int slabs = n / RY;
+    const int col_id = blockIdx.x / nch, ch_id = blockIdx.x - col_id * nch;
+    const int b = col_id / slabs, y0 = (col_id - b * slabs) * RY;
+    const int z0 = ch_id * zc, nz = min(zc, n - z0);
+    const size_t n3 = (size_t)n * n * n;
+    const uint16_t* xb = x + (size_t)b * n3 * CIN;
+    const uint16_t* db = dz + (size_t)b * n3 * COUT;
     const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63, h = l >> 5, col = l & 31;
-    // accumulator sets of this wave: taps t = wv + 4i (CIN 32) or tap groups
-    // g = wv + 4i (CIN 8: g = 3*dxi + gi, gi selects 4 of the 9 (dz, dy) pairs)
-    constexpr int NSET = CIN == 32 ? 7 : 3;
+
+    // rows o >= COUT of the dz copies stay zero
+    if constexpr (COUT < 32)
+        for (int i = tid; i < 3 * (32 - COUT) * DS; i += CONV_THR) {
+            const int sh = i / ((32 - COUT) * DS), rem = i - sh * (32 - COUT) * DS;
+            ds[(sh * 32 + COUT) * DS + rem] = 0;
+        }
+
+    // ---- plane loads (16-byte vectors of 8 channels of one cell)
+    constexpr int NVX16 = (CONV_CELLS / 16 + 2) * 16 * CIN / 8, NVX64 = (CONV_CELLS / 64 + 2) * 64 * CIN / 8;
+    constexpr int NLX = ((NVX16 > NVX64 ? NVX16 : NVX64) + CONV_THR - 1) / CONV_THR;
+    constexpr int NVD = CONV_CELLS * COUT / 8, NLD = (NVD + CONV_THR - 1) / CONV_THR;
+    const int nvx = xplane * CIN / 8;
+    u16x8 px[NLX], pd[NLD];
+    auto load_x = [&](int z) {
+        const int zz = (z + n) & (n - 1);
+#pragma unroll
+        for (int k = 0; k < NLX; ++k) {
+            const int i = tid + k * CONV_THR;
+            if (i < nvx) {
+                const int cell = i / (CIN / 8), cg = (i - cell * (CIN / 8)) * 8;
+                const int xx = cell & (n - 1), r = cell >> logn;
+                const int yy = (y0 - 1 + r + n) & (n - 1);
+                const size_t src = ((size_t)((zz << logn) + yy) << logn) + xx;
+                px[k] = *reinterpret_cast<const u16x8*>(xb + src * CIN + cg);
+            }
+        }
+    };
+    auto store_x = [&](int sl) {  // transposed to channel-major
+#pragma unroll
+        for (int k = 0; k < NLX; ++k) {
+            const int i = tid + k * CONV_THR;
+            if (i < nvx) {
+                const int cell = i / (CIN / 8), cg = (i - cell * (CIN / 8)) * 8;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) xs[((cg + q) * 3 + sl) * PS + cell] = px[k][q];
+            }
+        }
+    };
+    auto load_dz = [&](int z) {
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) {
+            const int i = tid + k * CONV_THR;
+            if (i < NVD) {
+                const int cell = i / (COUT / 8), og = (i - cell * (COUT / 8)) * 8;
+                const size_t src = ((size_t)z << (2 * logn)) + ((size_t)y0 << logn) + cell;
+                pd[k] = *reinterpret_cast<const u16x8*>(db + src * COUT + og);
+            }
+        }
+    };
+    float bacc[8] = {};  // bias partials of this thread's 8 output channels
+    auto store_dz = [&]() {  // transposed, in three copies shifted along x
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) {
+            const int i = tid + k * CONV_THR;
+            if (i < NVD) {
+                const int cell = i / (COUT / 8), og = (i - cell * (COUT / 8)) * 8;
+                const int xx = cell & (n - 1), rr = cell >> logn;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const uint16_t v = pd[k][q];
+                    bacc[q] += bf2f(v);
+#pragma unroll
+                    for (int sh = 0; sh < 3; ++sh)
+                        ds[(sh * 32 + og + q) * DS + rr * n + ((xx + sh - 1) & (n - 1))] = v;
+                }
+            }
+        }
+    };
+
+    // accumulator sets of this wave: taps t = wv + 8i (CIN 32) or tap groups
+    // g = wv + 8i (CIN 8: g = 3*dxi + gi, gi selects 4 of the 9 (dz, dy) pairs)
+    constexpr int NSET = CIN == 32 ? 4 : 2;
     floatx16 acc[NSET];
 #pragma unroll
     for (int i = 0; i < NSET; ++i) acc[i] = floatx16{};
-    float bpart = 0.0f;
 
-    for (int it = 0; it < WG_TILES; ++it) {
-        const int tile = blockIdx.x * WG_TILES + it;
-        if (tile >= tiles) break;  // uniform across the block
-        const int b = tile / tiles_per, c0 = (tile - b * tiles_per) * TILE;
-        const int k = c0 >> (2 * logn), j0 = (c0 >> logn) & (n - 1);
-        const uint16_t* xb = x + (size_t)b * n3 * CIN;
-        const uint16_t* db = dz + (size_t)b * n3 * COUT;
+    load_x(z0 - 1);
+    store_x(0);
+    load_x(z0);
+    store_x(1);
+    load_x(z0 + 1);
+    load_dz(z0);
+    for (int p = 0; p < nz; ++p) {
+        store_x((p + 2) % 3);  // plane z0+p+1 replaces plane z0+p-2
+        store_dz();            // plane z0+p
         __syncthreads();
-        // x neighbourhood, transposed to channel-major rows
-        const int xcells = 3 * (R + 2) * n;
-        for (int i = tid; i < xcells * CIN / 8; i += NTHR) {
-            const int cell = i / (CIN / 8), cg = (i - cell * (CIN / 8)) * 8;
-            const int xx = cell & (n - 1), rp = cell >> logn;
-            const int r = rp % (R + 2), p = rp / (R + 2);
-            const int zz = (k - 1 + p + n) & (n - 1), yy = (j0 - 1 + r + n) & (n - 1);
-            const u16x8 v = *reinterpret_cast<const u16x8*>(
-                xb + (size_t)((((zz << logn) + yy) << logn) + xx) * CIN + cg);
-#pragma unroll
-            for (int q = 0; q < 8; ++q) xs[(cg + q) * xcells + cell] = v[q];
+        if (p + 1 < nz) {
+            load_x(z0 + p + 2);
+            load_dz(z0 + p + 1);
         }
-        // dz tile, transposed, in three copies shifted along x: copy s holds
-        // dz(q - (s - 1)) at position q
-        for (int i = tid; i < TILE * 32; i += NTHR) {
-            const int cell = i >> 5, o = i & 31;
-            const int xx = cell & (n - 1), rr = cell >> logn;
-            const uint16_t v = o < COUT ? db[(size_t)(c0 + cell) * COUT + o] : (uint16_t)0;
-#pragma unroll
-            for (int s = 0; s < 3; ++s) {
-                const int q = (xx + s - 1) & (n - 1);
-                ds[((s * 32 + o) * R + rr) * n + q] = v;
-            }
-        }
-        // bias partial: thread tid sums dz[.][tid & 31] over cells tid>>5, +8, ...
-        if ((tid & 31) < COUT)
-            for (int cell = tid >> 5; cell < TILE; cell += 8)
-                bpart += bf2f(db[(size_t)(c0 + cell) * COUT + (tid & 31)]);
-        __syncthreads();
-
+        const int sb[3] = {p % 3, (p + 1) % 3, (p + 2) % 3};  // ring slot of plane dz = -1, 0, 1
 #pragma unroll
         for (int si = 0; si < NSET; ++si) {
-            const int set = wv + 4 * si;
+            const int set = wv + 8 * si;
             if (set >= 27 || (CIN == 8 && set >= 9)) break;  // uniform per wave
-            int dxs, dzv[4], dyv[4];
+            int dxs, dzv = 0, dyv = 0;
             if constexpr (CIN == 32) {
                 dxs = set % 3;  // shift copy s = dx + 1
-                dzv[0] = set / 9 - 1;
-                dyv[0] = (set / 3) % 3 - 1;
+                dzv = set / 9 - 1;
+                dyv = (set / 3) % 3 - 1;
             } else {
                 dxs = set / 3;
-                const int gi = set % 3;  // (dz, dy) pairs 4gi .. 4gi+3 of 9
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int pr = 4 * gi + q;
-                    dzv[q] = pr / 3 - 1;
-                    dyv[q] = pr % 3 - 1;
-                }
             }
-#pragma unroll 2
-            for (int kc = 0; kc < TILE / 16; ++kc) {
+#pragma unroll 4
+            for (int kc = 0; kc < CONV_CELLS / 16; ++kc) {
                 const int cell = kc * 16 + 8 * h;
                 const int rr = cell >> logn, xq = cell & (n - 1);
-                const bf16x8 a = frag(ds + ((dxs * 32 + col) * R + rr) * n + xq);
+                const bf16x8 a = frag(ds + (dxs * 32 + col) * DS + rr * n + xq);
                 bf16x8 bb = {};
                 if constexpr (CIN == 32) {
-                    bb = frag(xs + ((col * 3 + dzv[0] + 1) * (R + 2) + rr + dyv[0] + 1) * n + xq);
+                    bb = frag(xs + (col * 3 + sb[dzv + 1]) * PS + (rr + dyv + 1) * n + xq);
                 } else {
                     const int tg = col >> 3, c = col & 7, pr = 4 * (set % 3) + tg;
                     if (pr < 9) {
                         const int dzz = pr / 3 - 1, dyy = pr % 3 - 1;
-                        bb = frag(xs + ((c * 3 + dzz + 1) * (R + 2) + rr + dyy + 1) * n + xq);
+                        bb = frag(xs + (c * 3 + sb[dzz + 1]) * PS + (rr + dyy + 1) * n + xq);
                     }
                 }
                 acc[si] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, acc[si], 0, 0, 0);
             }
         }
+        __syncthreads();  // reads of plane z0+p-1 and of the dz plane are done
     }
 
-    // ---- write this block's partial sums: ws[block][t][o][c]
+    // ---- this block's partial sums: ws[block][t][o][c], wsb[block][o]
     float* wb = ws + (size_t)blockIdx.x * 27 * 32 * 32;
 #pragma unroll
     for (int si = 0; si < NSET; ++si) {
-        const int set = wv + 4 * si;
+        const int set = wv + 8 * si;
         if (set >= 27 || (CIN == 8 && set >= 9)) break;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
@@ -318,11 +394,13 @@ __global__ __launch_bounds__(NTHR) void k_wgrad(const uint16_t* __restrict__ x,
             wb[(t * 32 + o) * 32 + c] = acc[si][r];
         }
     }
-    bsum[tid] = bpart;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) bsum[tid * 8 + q] = bacc[q];
     __syncthreads();
-    if (tid < 32) {
+    if (tid < COUT) {  // output channel o = tid: threads with og = 8 (o / 8), in order
+        const int g = tid >> 3, q = tid & 7;
         float sacc = 0.0f;
-        for (int i = 0; i < 8; ++i) sacc += bsum[i * 32 + tid];
+        for (int j = g; j < (NVD < CONV_THR ? NVD : CONV_THR); j += COUT / 8) sacc += bsum[j * 8 + q];
         wsb[blockIdx.x * 32 + tid] = sacc;
     }
 }
@@ -332,19 +410,35 @@ __global__ __launch_bounds__(NTHR) void k_wgrad_reduce(const float* __restrict__
                                                        int cin, int cout, float* __restrict__ dw,
                                                        float* __restrict__ dbias)
 {
-    const int i = blockIdx.x * NTHR + threadIdx.x;  // over cout*27*cin, then cout biases
+    // one thread per weight (then per bias); the partials of consecutive
+    // blocks are fetched 8 at a time and added in block order
+    const int i = blockIdx.x * NTHR + threadIdx.x;
     const int nw = cout * 27 * cin;
+    if (i >= nw + cout) return;
+    const float* src;
+    size_t stride;
     if (i < nw) {
         const int o = i / (27 * cin), rem = i - o * 27 * cin, t = rem / cin, c = rem - t * cin;
-        float s = 0.0f;
-        for (int b = 0; b < nblocks; ++b) s += ws[((size_t)b * 27 * 32 + t * 32 + o) * 32 + c];
-        dw[i] = s;
-    } else if (i < nw + cout) {
-        const int o = i - nw;
-        float s = 0.0f;
-        for (int b = 0; b < nblocks; ++b) s += wsb[b * 32 + o];
-        dbias[o] = s;
+        src = ws + (size_t)(t * 32 + o) * 32 + c;
+        stride = 27 * 32 * 32;
+    } else {
+        src = wsb + (i - nw);
+        stride = 32;
     }
+    float s = 0.0f;
+    int bk = 0;
+    for (; bk + 8 <= nblocks; bk += 8) {
+        float v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = src[(size_t)(bk + j) * stride];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s += v[j];
+    }
+    for (; bk < nblocks; ++bk) s += src[(size_t)bk * stride];
+    if (i < nw)
+        dw[i] = s;
+    else
+        dbias[i - nw] = s;
 }
 
 // ------------------------------------------------------------ elementwise
@@ -541,9 +635,29 @@ bool conv_n_ok(int n) { return n == 16 || n == 32 || n == 64; }
 
 int status(hipError_t e) { return e == hipSuccess ? MHD_OK : MHD_ERR_DEVICE; }
 
-size_t wgrad_lds(int cin, int n) { return 2 * (cin * 3 * (TILE / n + 2) * n + 3 * 32 * TILE); }
+size_t wgrad_lds(int cin, int n)
+{
+    return 2 * (cin * 3 * ((CONV_CELLS / n + 2) * n + 8) + 3 * 32 * (CONV_CELLS + 8)) +
+           4 * CONV_THR * 8;
+}
 
-size_t conv_lds(int cin, int n) { return 2 * (32 * 27 * cin + 3 * (CONV_CELLS / n + 2) * n * cin); }
+// Slabs of CONV_CELLS cells per plane and z chunks of zc planes, so that
+// about one block per CU (256) marches at once: blocks = columns * nch.
+void conv_chunks(int n, int batch, int& columns, int& nch, int& zc)
+{
+    columns = batch * (n / (CONV_CELLS / n));
+    nch = (256 + columns - 1) / columns;
+    nch = nch < 1 ? 1 : nch > n / 4 ? n / 4 : nch;
+    zc = (n + nch - 1) / nch;
+    nch = (n + zc - 1) / zc;
+}
+
+size_t conv_lds(int cin, int n)
+{
+    const int cp = cin == 32 ? conv_cp<32>() : conv_cp<8>();
+    const int wrow = cin == 32 ? conv_wrow<32>() : conv_wrow<8>();
+    return 2 * (32 * wrow + 3 * (CONV_CELLS / n + 2) * n * cp);
+}
 
 template <int CIN, int MODE>
 hipError_t launch_conv(const uint16_t* x, const uint16_t* w, const float* bias, const uint16_t* zp,
@@ -559,12 +673,8 @@ hipError_t launch_conv(const uint16_t* x, const uint16_t* w, const float* bias, 
         if (e != hipSuccess) return e;
         attr = true;
     }
-    // z chunks so that about 256 blocks (one per CU) march at once
-    const int columns = batch * (n / (CONV_CELLS / n));
-    int nch = (256 + columns - 1) / columns;
-    nch = nch < 1 ? 1 : nch > n / 4 ? n / 4 : nch;
-    const int zc = (n + nch - 1) / nch;
-    nch = (n + zc - 1) / zc;
+    int columns, nch, zc;
+    conv_chunks(n, batch, columns, nch, zc);
     hipLaunchKernelGGL((k_conv<CIN, MODE>), dim3(columns * nch), dim3(CONV_THR),
                        conv_lds(CIN, n), st, x, w, bias, zp, n, ilog2(n), nch, zc, cout, o0, o1,
                        of);
@@ -584,11 +694,12 @@ hipError_t launch_wgrad(const uint16_t* x, const uint16_t* dz, int n, int batch,
         if (e != hipSuccess) return e;
         attr = true;
     }
-    const int tiles = n * n * n / TILE * batch;
-    const int blocks = (tiles + WG_TILES - 1) / WG_TILES;
+    int columns, nch, zc;
+    conv_chunks(n, batch, columns, nch, zc);
+    const int blocks = columns * nch;
     float* wsb = ws + (size_t)blocks * 27 * 32 * 32;
-    hipLaunchKernelGGL((k_wgrad<CIN, COUT>), dim3(blocks), dim3(NTHR), wgrad_lds(CIN, n), st, x,
-                       dz, n, ilog2(n), batch, ws, wsb);
+    hipLaunchKernelGGL((k_wgrad<CIN, COUT>), dim3(blocks), dim3(CONV_THR), wgrad_lds(CIN, n), st,
+                       x, dz, n, ilog2(n), nch, zc, ws, wsb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int total = COUT * 27 * CIN + COUT;
@@ -680,9 +791,9 @@ int mhdnn_conv3d_dgrad(const uint16_t* dz, const uint16_t* wt_pad, const uint16_
 int64_t mhdnn_wgrad_workspace_floats(int32_t n, int32_t batch)
 {
     if (!conv_n_ok(n) || batch < 1) return 0;
-    const int64_t tiles = (int64_t)n * n * n / TILE * batch;
-    const int64_t blocks = (tiles + WG_TILES - 1) / WG_TILES;
-    return blocks * (27 * 32 * 32 + 32);
+    int columns, nch, zc;
+    conv_chunks(n, batch, columns, nch, zc);
+    return (int64_t)columns * nch * (27 * 32 * 32 + 32);
 }
 
 int mhdnn_conv3d_wgrad(const uint16_t* x, const uint16_t* dz, int32_t n, int32_t batch,

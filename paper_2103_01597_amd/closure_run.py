@@ -56,10 +56,17 @@ def main():
     ap.add_argument("--kmax", type=int, default=8)
     ap.add_argument("--u-amp", type=float, default=0.1)
     ap.add_argument("--fine-prec", default="f64")
+    ap.add_argument("--conv-only", action="store_true",
+                    help="only time the network's forward and backward at the coarse size "
+                         "(batch --batch) and print that JSON line")
     args = ap.parse_args()
 
     import torch
     from . import closure, mhd, nn
+    if args.conv_only:
+        nn.lib()
+        print(json.dumps(conv_throughput(torch, nn, args.n_fine // 4, args.batch)), flush=True)
+        return
     log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
     amp = (0.0, args.u_amp, args.u_amp, args.u_amp, 0.0, 1e-2, 1e-2, 1e-2)
     nc = args.n_fine // 4

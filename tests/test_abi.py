@@ -98,6 +98,14 @@ def test_null_arguments(L):
     assert L.mhd_step(None, arr, ctypes.byref(cur), vp(3), None, 1e-3, 1, None) == 1
     out = ctypes.c_double()
     assert L.mhd_reduce(None, vp(1), 0, 0, ctypes.byref(out), None) == 1
+    box = mhd.Box(0, 1, 0, 1, 0, 1)
+    assert L.mhd_rk3_substep_box(None, 0, ctypes.byref(box), vp(1), vp(2), vp(3), None, 1e-3,
+                                 None) == 1
+    assert L.mhd_halo_pack(None, vp(1), vp(2), None) == 1
+    assert L.mhd_halo_unpack(None, vp(1), vp(2), None) == 1
+    assert L.mhd_halo_exchange_self(None, vp(1), vp(2), vp(3), None) == 1
+    assert L.mhd_step_segmented(None, arr, ctypes.byref(cur), vp(3), None, 1e-3, 1, vp(4), vp(5),
+                                None, None) == 1
     L.mhd_finalize(None)
 
 

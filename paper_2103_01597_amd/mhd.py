@@ -145,6 +145,7 @@ class Solver:
         self.kernel = {v: k for k, v in KERNELS.items()}[int(self.layout.kernel)]
 
     def close(self):
+        self._segbufs = None
         if self._ctx:
             lib().mhd_finalize(self._ctx)
             self._ctx = ctypes.c_void_p()
@@ -252,11 +253,16 @@ class Solver:
     def step_segmented(self, f, cur, w, comp=None, dt=1e-3, nsteps=1, sendbuf=None,
                        recvbuf=None, stream=None, comm_stream=None) -> int:
         """mhd_step with the inner/outer split and the packed halo exchange on
-        comm_stream; returns the result's index."""
+        comm_stream; returns the result's index.  Without explicit buffers the
+        solver's own pair is used (allocated once and kept, so that no buffer
+        is freed while queued work may still use it)."""
         arr = (ctypes.c_void_p * 2)(f[0].data_ptr(), f[1].data_ptr())
         c = ctypes.c_int32(cur)
-        sendbuf = self.segment_buffer() if sendbuf is None else sendbuf
-        recvbuf = self.segment_buffer() if recvbuf is None else recvbuf
+        if sendbuf is None or recvbuf is None:
+            if getattr(self, "_segbufs", None) is None:
+                self._segbufs = (self.segment_buffer(), self.segment_buffer())
+            sendbuf = self._segbufs[0] if sendbuf is None else sendbuf
+            recvbuf = self._segbufs[1] if recvbuf is None else recvbuf
         _check("mhd_step_segmented",
                lib().mhd_step_segmented(self._ctx, arr, ctypes.byref(c), _ptr(w), _ptr(comp), dt,
                                         nsteps, _ptr(sendbuf), _ptr(recvbuf), _stream(stream),

@@ -130,15 +130,17 @@ def test_box_rejects_out_of_range(mhd):
     S.close()
 
 
+@pytest.mark.parametrize("same_stream", [False, True])
 @pytest.mark.parametrize("prec", ["f64", "f32c"])
 @pytest.mark.parametrize("n", [(48, 40, 24), (64, 64, 64), (19, 6, 11), (100, 40, 72)])
-def test_segmented_step_equals_step(mhd, prec, n):
+def test_segmented_step_equals_step(mhd, prec, n, same_stream):
     import torch
-    say(f"segmented step {prec} {n}")
+    say(f"segmented step {prec} {n} same_stream={same_stream}")
     S = mhd.Solver(*n, prec)
     f0 = inputs.fourier_modes(n, 3, 0.05, seed=24)
     res = []
-    comm = torch.cuda.Stream()
+    # the exchange on its own stream, or on the launch stream itself (serial)
+    comm = torch.cuda.current_stream() if same_stream else torch.cuda.Stream()
     for segmented in (False, True):
         f = [S.upload(f0), S.empty()]
         w = S.zeros()

@@ -36,21 +36,31 @@ namespace {
 #ifndef MHD_SPLIT_TX
 #define MHD_SPLIT_TX 32
 #endif
-constexpr int R = 3;  // this kernel is built for the sixth-order stencil only
 constexpr int TX = MHD_SPLIT_TX, TY = 256 / MHD_SPLIT_TX, NC = TX * TY;  // cells per tile plane
 constexpr int NTH = 2 * NC;                    // threads: two groups of NC
-constexpr int HX = TX + 2 * R, HY = TY + 2 * R, PLANE = HX * HY;  // 38 x 14 = 532
-constexpr int SLOT = NQ * PLANE;
-constexpr int NSLOT = 4;
-constexpr int FULL = PLANE / NC;   // plane elements per field every thread of a group loads
-constexpr int EXTRA = PLANE % NC;  // threads that load one more
 constexpr int NXF = 10;            // values F hands to M
 constexpr int NXM = 7;             // values M hands to F
+// Per stencil radius RAD: the halo'd tile plane (38 x 14 = 532 cells at
+// RAD = 3) and the LDS ring of RAD + 1 such planes of all 8 fields.
+template <int RAD>
+struct SRing {
+    static constexpr int HX = TX + 2 * RAD, HY = TY + 2 * RAD, PLANE = HX * HY;
+    static constexpr int SLOT = NQ * PLANE;
+    static constexpr int NSLOT = RAD + 1;
+    static constexpr int FULL = PLANE / NC;   // plane elements per field every thread of a group loads
+    static constexpr int EXTRA = PLANE % NC;  // threads that load one more
+};
 
-template <int PREC>
-constexpr size_t ring_bytes() { return sizeof(typename Prec<PREC>::T) * NSLOT * SLOT; }
-template <int PREC>
-constexpr size_t lds_bytes() { return ring_bytes<PREC>() + sizeof(typename Prec<PREC>::Rt) * NXF * NC; }
+template <int PREC, int RAD>
+constexpr size_t ring_bytes()
+{
+    return sizeof(typename Prec<PREC>::T) * SRing<RAD>::NSLOT * SRing<RAD>::SLOT;
+}
+template <int PREC, int RAD>
+constexpr size_t lds_bytes()
+{
+    return ring_bytes<PREC, RAD>() + sizeof(typename Prec<PREC>::Rt) * NXF * NC;
+}
 
 static_assert(NXM <= NXF, "M's values reuse the entries of F's");
 
@@ -71,11 +81,11 @@ struct TileMap {
 
 // Per-axis scale factors of the integer-weight stencils.
 struct Scales {
-    double d1[3];   // 1/(60 h_a)
-    double d2[3];   // 1/(180 h_a^2)
-    double mxy;     // 1/(720 h_x h_y)
-    double wxz[3];  // {270, -27, 2}/(720 h_x h_z)
-    double wyz[3];  // {270, -27, 2}/(720 h_y h_z)
+    double d1[3];      // 1/(DEN1 h_a)
+    double d2[3];      // 1/(DEN2 h_a^2)
+    double mxy;        // 1/(4 DEN2 h_x h_y)
+    double wxz[RMAX];  // W2(r, m)/(4 DEN2 h_x h_z), m = 1..r
+    double wyz[RMAX];  // W2(r, m)/(4 DEN2 h_y h_z)
 };
 
 constexpr int NO_TILE = -1;
@@ -120,7 +130,7 @@ __device__ __forceinline__ int tile_of_block(int b, const TileMap& m)
     return t < r * m.round + rem ? t : NO_TILE;
 }
 
-template <int PREC>
+template <int PREC, int RAD>
 __global__ __launch_bounds__(NTH, blocks_per_cu<PREC>()) void k_rk3_split(Grid g, const Phys* P_dev, Scales sc, TileMap map, int s,
                                                      const typename Prec<PREC>::T* __restrict__ fin,
                                                      typename Prec<PREC>::T* __restrict__ fout,
@@ -137,7 +147,9 @@ __global__ __launch_bounds__(NTH, blocks_per_cu<PREC>()) void k_rk3_split(Grid g
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* __restrict__ lds = reinterpret_cast<T*>(smem_raw);
     // exchange area past the ring: F's NXF values per cell, then (in place) M's NXM
-    Rt* __restrict__ xch = reinterpret_cast<Rt*>(smem_raw + ring_bytes<PREC>());  // [NXF][NC]
+    Rt* __restrict__ xch = reinterpret_cast<Rt*>(smem_raw + ring_bytes<PREC, RAD>());  // [NXF][NC]
+    constexpr int HX = SRing<RAD>::HX, PLANE = SRing<RAD>::PLANE, SLOT = SRing<RAD>::SLOT;
+    constexpr int NSLOT = SRing<RAD>::NSLOT, FULL = SRing<RAD>::FULL, EXTRA = SRing<RAD>::EXTRA;
 
     const int tile = tile_of_block(blockIdx.x, map);
     if (tile == NO_TILE) return;  // the whole workgroup exits together
@@ -182,7 +194,7 @@ __global__ __launch_bounds__(NTH, blocks_per_cu<PREC>()) void k_rk3_split(Grid g
 
         T pre[4][NLOAD];
         auto load_plane = [&](int t) {
-            const unsigned zo = (unsigned)((t + R) * g.mxy);
+            const unsigned zo = (unsigned)((t + RAD) * g.mxy);
 #pragma unroll
             for (int k4 = 0; k4 < 4; ++k4) {
                 const T* f = field_ptr(fin, q0 + k4);
@@ -213,46 +225,47 @@ __global__ __launch_bounds__(NTH, blocks_per_cu<PREC>()) void k_rk3_split(Grid g
         // V(slot, q, dy, dx): field q of the ring slot at offset (dx, dy) from the
         // thread's cell.  Addressed from the cell's stencil corner so that every
         // offset is a non-negative constant the LDS instructions take as an immediate.
-        const int corner = ly * HX + lx;  // cell (x - R, y - R) within a plane
+        const int corner = ly * HX + lx;  // cell (x - RAD, y - RAD) within a plane
         auto V = [&](int slot, int q, int dy, int dx) -> T {
-            return lds[(slot * SLOT + corner) + (q * PLANE + (dy + R) * HX + (dx + R))];
+            return lds[(slot * SLOT + corner) + (q * PLANE + (dy + RAD) * HX + (dx + RAD))];
         };
 
-        // ---- z state of the group's fields: own-column history (t-3, t-2, t-1),
+        // ---- z state of the group's fields: own-column history (t-RAD .. t-1),
         // indexed by field within the group, and the carried past halves of the
-        // group's three xz/yz mixed combinations:
+        // group's three xz/yz mixed combinations (past[cb][k]: output t+1+k):
         //   F: 0 Dxz uz, 1 Dyz uz, 2 Dxz ux + Dyz uy
         //   M: 0 Dxz Az, 1 Dyz Az, 2 Dxz Ax + Dyz Ay
-        T hist[3][4];
-        D2 past[3][3];
+        T hist[RAD][4];
+        D2 past[3][RAD];
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
+        for (int k = 0; k < RAD; ++k)
 #pragma unroll
             for (int q = 0; q < 4; ++q) hist[k][q] = T(0);
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
-            for (int k = 0; k < 3; ++k) past[c][k] = D2(0);
+            for (int k = 0; k < RAD; ++k) past[c][k] = D2(0);
         T wold[4] = {}, cc[4] = {};
 
         auto cell_index = [&](int t) { return g.interior + t * g.mxy + (y0 + ly) * g.mx + (x0 + lx); };
 
-        constexpr int SOFS = 8;
-        load_plane(bz0 - 3);
+        constexpr int SOFS = 4 * NSLOT;  // keeps (t + SOFS) non-negative for slot arithmetic
+        load_plane(bz0 - RAD);
         // u: plane index relative to the box start, so that the warm-up tests
         // below compare against constants
-        for (int u = -7; u < bz1 - bz0; ++u) {
+        for (int u = -(2 * RAD + 1); u < bz1 - bz0; ++u) {
             const int t = bz0 + u;
             // warm-up planes (t < z0) run the whole computation too (branch-free
             // code schedules better); only their z state is kept
-            const int s0 = (t + SOFS) & 3;
-            const bool live = u >= -3;  // uniform: plane t is in the ring
+            const int s0 = (t + SOFS) % NSLOT;
+            const bool live = u >= -RAD;  // uniform: plane t is in the ring
             Derivs<Rt> d;
             T fc[4], wnew[4], fnew[4], cnew[4];
             Rt S[3][3], divu = Rt(0), SS = Rt(0), B[3], J[3], jxB[3];
             if (live) {
-                const int s1 = (t + 1 + SOFS) & 3, s2 = (t + 2 + SOFS) & 3, s3 = (t + 3 + SOFS) & 3;
-                const int sl[4] = {s0, s1, s2, s3};
+                int sl[RAD + 1];  // ring slots of planes t .. t+RAD
+#pragma unroll
+                for (int k = 0; k <= RAD; ++k) sl[k] = (t + k + SOFS) % NSLOT;
 
                 auto sum2 = [&](int q, int dir, int m) {
                     return dir == 0 ? D2(V(s0, q, 0, m)) + D2(V(s0, q, 0, -m))
@@ -263,33 +276,45 @@ __global__ __launch_bounds__(NTH, blocks_per_cu<PREC>()) void k_rk3_split(Grid g
                         return dir == 0 ? Rt(V(s0, q, 0, m)) - Rt(V(s0, q, 0, -m))
                                         : Rt(V(s0, q, m, 0)) - Rt(V(s0, q, -m, 0));
                     };
-                    return (Rt(45) * g1(1) - Rt(9) * g1(2) + g1(3)) * Rt(sc.d1[dir]);
+                    Rt acc = Rt(W1(RAD, 1)) * g1(1);
+#pragma unroll
+                    for (int m = 2; m <= RAD; ++m) acc += Rt(W1(RAD, m)) * g1(m);
+                    return acc * Rt(sc.d1[dir]);
                 };
-                // own column of field q (group-local index k4), plane t+k, k = -3..3
+                // own column of field q (group-local index k4), plane t+k, k = -RAD..RAD
                 auto col = [&](int q, int k4, int k) -> T {
-                    return k < 0 ? hist[k + 3][k4] : V(sl[k], q, 0, 0);
+                    return k < 0 ? hist[k + RAD][k4] : V(sl[k], q, 0, 0);
                 };
                 auto dz1 = [&](int q, int k4) -> Rt {
-                    return (Rt(45) * (Rt(col(q, k4, 1)) - Rt(col(q, k4, -1))) -
-                            Rt(9) * (Rt(col(q, k4, 2)) - Rt(col(q, k4, -2))) +
-                            (Rt(col(q, k4, 3)) - Rt(col(q, k4, -3)))) * Rt(sc.d1[2]);
+                    Rt acc = Rt(W1(RAD, 1)) * (Rt(col(q, k4, 1)) - Rt(col(q, k4, -1)));
+#pragma unroll
+                    for (int m = 2; m <= RAD; ++m)
+                        acc += Rt(W1(RAD, m)) * (Rt(col(q, k4, m)) - Rt(col(q, k4, -m)));
+                    return acc * Rt(sc.d1[2]);
                 };
                 auto second = [&](int q, int k4, D2& xx, D2& yy, D2& zz) {
-                    const D2 f0 = D2(-490) * D2(V(s0, q, 0, 0));
-                    xx = (D2(270) * sum2(q, 0, 1) - D2(27) * sum2(q, 0, 2) + D2(2) * sum2(q, 0, 3) + f0) *
-                         D2(sc.d2[0]);
-                    yy = (D2(270) * sum2(q, 1, 1) - D2(27) * sum2(q, 1, 2) + D2(2) * sum2(q, 1, 3) + f0) *
-                         D2(sc.d2[1]);
-                    zz = (D2(270) * (D2(col(q, k4, 1)) + D2(col(q, k4, -1))) -
-                          D2(27) * (D2(col(q, k4, 2)) + D2(col(q, k4, -2))) +
-                          D2(2) * (D2(col(q, k4, 3)) + D2(col(q, k4, -3))) + f0) * D2(sc.d2[2]);
+                    const D2 f0 = D2(W2(RAD, 0)) * D2(V(s0, q, 0, 0));
+                    D2 ax = D2(W2(RAD, 1)) * sum2(q, 0, 1), ay = D2(W2(RAD, 1)) * sum2(q, 1, 1);
+                    D2 az = D2(W2(RAD, 1)) * (D2(col(q, k4, 1)) + D2(col(q, k4, -1)));
+#pragma unroll
+                    for (int m = 2; m <= RAD; ++m) {
+                        ax += D2(W2(RAD, m)) * sum2(q, 0, m);
+                        ay += D2(W2(RAD, m)) * sum2(q, 1, m);
+                        az += D2(W2(RAD, m)) * (D2(col(q, k4, m)) + D2(col(q, k4, -m)));
+                    }
+                    xx = (ax + f0) * D2(sc.d2[0]);
+                    yy = (ay + f0) * D2(sc.d2[1]);
+                    zz = (az + f0) * D2(sc.d2[2]);
                 };
                 auto dxy = [&](int q) -> D2 {
                     auto e = [&](int m) {
                         return (D2(V(s0, q, m, m)) + D2(V(s0, q, -m, -m))) -
                                (D2(V(s0, q, -m, m)) + D2(V(s0, q, m, -m)));
                     };
-                    return (D2(270) * e(1) - D2(27) * e(2) + D2(2) * e(3)) * D2(sc.mxy);
+                    D2 acc = D2(W2(RAD, 1)) * e(1);
+#pragma unroll
+                    for (int m = 2; m <= RAD; ++m) acc += D2(W2(RAD, m)) * e(m);
+                    return acc * D2(sc.mxy);
                 };
                 // xz (dir 0) / yz (dir 1) mixed derivative of field q for the
                 // group's combination cb; see the single-group tiled kernel.
@@ -299,18 +324,17 @@ __global__ __launch_bounds__(NTH, blocks_per_cu<PREC>()) void k_rk3_split(Grid g
                         return dir == 0 ? D2(V(slot, q, 0, m)) - D2(V(slot, q, 0, -m))
                                         : D2(V(slot, q, m, 0)) - D2(V(slot, q, -m, 0));
                     };
-                    D2 res = D2(wm[0]) * dd(s1, 1) + D2(wm[1]) * dd(s2, 2) + D2(wm[2]) * dd(s3, 3);
+                    D2 res = D2(wm[0]) * dd(sl[1], 1);
+#pragma unroll
+                    for (int m = 2; m <= RAD; ++m) res += D2(wm[m - 1]) * dd(sl[m], m);
                     if (first_of_combo) res -= past[cb][0];
-                    const D2 c1 = D2(wm[0]) * dd(s0, 1), c2 = D2(wm[1]) * dd(s0, 2),
-                             c3 = D2(wm[2]) * dd(s0, 3);
-                    if (first_of_combo) {
-                        past[cb][0] = past[cb][1] + c1;
-                        past[cb][1] = past[cb][2] + c2;
-                        past[cb][2] = c3;
-                    } else {
-                        past[cb][0] += c1;
-                        past[cb][1] += c2;
-                        past[cb][2] += c3;
+#pragma unroll
+                    for (int m = 1; m <= RAD; ++m) {
+                        const D2 c = D2(wm[m - 1]) * dd(s0, m);
+                        if (first_of_combo)
+                            past[cb][m - 1] = m < RAD ? past[cb][m < RAD ? m : 0] + c : c;
+                        else
+                            past[cb][m - 1] += c;
                     }
                     return res;
                 };
@@ -420,9 +444,9 @@ __global__ __launch_bounds__(NTH, blocks_per_cu<PREC>()) void k_rk3_split(Grid g
 #pragma unroll
                 for (int k4 = 0; k4 < 4; ++k4) {
                     fc[k4] = V(s0, q0 + k4, 0, 0);
-                    hist[0][k4] = hist[1][k4];
-                    hist[1][k4] = hist[2][k4];
-                    hist[2][k4] = fc[k4];
+#pragma unroll
+                    for (int k = 0; k + 1 < RAD; ++k) hist[k][k4] = hist[k + 1][k4];
+                    hist[RAD - 1][k4] = fc[k4];
                 }
 
                 if constexpr (G == 0) {
@@ -438,11 +462,11 @@ __global__ __launch_bounds__(NTH, blocks_per_cu<PREC>()) void k_rk3_split(Grid g
             }
 
             // Every read of plane t is done and F's values are visible: plane
-            // t+4 replaces plane t in the ring, and M takes F's values and puts
+            // t+RAD+1 replaces plane t in the ring, and M takes F's values and puts
             // its own in their place (each thread only touches the entries of
             // its own cell, so program order separates the read and the write).
             __syncthreads();
-            store_plane((t + 4 + SOFS) & 3);
+            store_plane((t + RAD + 1 + SOFS) % NSLOT);
             if constexpr (G == 1) {
                 if (live) {
                     d.lnrho = xch[0 * NC + tid];
@@ -459,7 +483,7 @@ __global__ __launch_bounds__(NTH, blocks_per_cu<PREC>()) void k_rk3_split(Grid g
                     for (int i = 0; i < NXM; ++i) xch[i * NC + tid] = v[i];
                 }
             }
-            __syncthreads();  // plane t+4 and M's values visible
+            __syncthreads();  // plane t+RAD+1 and M's values visible
 
             if (live) {
                 // the physics constants are read here, per plane, from device
@@ -485,11 +509,11 @@ __global__ __launch_bounds__(NTH, blocks_per_cu<PREC>()) void k_rk3_split(Grid g
                 }
             }
 
-            // plane t+5 and the next plane's register values are fetched before
+            // plane t+RAD+2 and the next plane's register values are fetched before
             // this plane's results go out: the vector-memory counter covers loads
             // and stores alike in issue order, so the next plane's waits for the
             // loads do not also wait for these stores
-            if (t + 5 <= bz1 + 2) load_plane(t + 5);
+            if (t + RAD + 2 <= bz1 + RAD - 1) load_plane(t + RAD + 2);
             if (active && u + 1 >= 0 && t + 1 < bz1) {
                 const unsigned c = (unsigned)cell_index(t + 1);
                 if (s > 0) {
@@ -518,19 +542,19 @@ __global__ __launch_bounds__(NTH, blocks_per_cu<PREC>()) void k_rk3_split(Grid g
         march(std::integral_constant<int, 1>{});
 }
 
-template <int PREC>
+template <int PREC, int RAD>
 hipError_t launch_one(const Grid& g, const Phys& P, const Phys* P_dev, const Box& bx, int s,
                       const void* f_in, void* f_out, void* w, void* comp, double dt, hipStream_t st)
 {
     using T = typename Prec<PREC>::T;
     static int round = -1;  // resident workgroups per round on this device
-    const size_t lds = lds_bytes<PREC>();
+    constexpr size_t lds = lds_bytes<PREC, RAD>();
     if (round < 0) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_rk3_split<PREC>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_rk3_split<PREC, RAD>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         int per_cu = 0, dev = 0, cus = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rk3_split<PREC>, NTH, lds);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rk3_split<PREC, RAD>, NTH, lds);
         if (e != hipSuccess) return e;
         e = hipGetDevice(&dev);
         if (e != hipSuccess) return e;
@@ -543,36 +567,57 @@ hipError_t launch_one(const Grid& g, const Phys& P, const Phys* P_dev, const Box
     m.nty = (bx.y1 - bx.y0 + TY - 1) / TY;
     m.round = round;
     z_chunks(m, bx.z1 - bx.z0);
-    Scales sc;
+    Scales sc{};
     for (int a = 0; a < 3; ++a) {
-        sc.d1[a] = P.inv_h[a] / 60.0;
-        sc.d2[a] = P.inv_h[a] * P.inv_h[a] / 180.0;
+        sc.d1[a] = P.inv_h[a] / DEN1(RAD);
+        sc.d2[a] = P.inv_h[a] * P.inv_h[a] / DEN2(RAD);
     }
-    sc.mxy = P.inv_h[0] * P.inv_h[1] / 720.0;
-    const double wm[3] = {270.0, -27.0, 2.0};
-    for (int k = 0; k < 3; ++k) {
-        sc.wxz[k] = wm[k] * P.inv_h[0] * P.inv_h[2] / 720.0;
-        sc.wyz[k] = wm[k] * P.inv_h[1] * P.inv_h[2] / 720.0;
+    sc.mxy = P.inv_h[0] * P.inv_h[1] / (4.0 * DEN2(RAD));
+    for (int k = 1; k <= RAD; ++k) {
+        sc.wxz[k - 1] = W2(RAD, k) * P.inv_h[0] * P.inv_h[2] / (4.0 * DEN2(RAD));
+        sc.wyz[k - 1] = W2(RAD, k) * P.inv_h[1] * P.inv_h[2] / (4.0 * DEN2(RAD));
     }
     const int tiles = m.ntx * m.nty * m.nch;
     const int blocks = (round > 0 && (round & 7) == 0) ? (tiles + round - 1) / round * round : tiles;
-    hipLaunchKernelGGL(k_rk3_split<PREC>, dim3(blocks), dim3(NTH), lds, st, g, P_dev, sc, m, s,
-                       (const T*)f_in, (T*)f_out, (T*)w, (T*)comp, dt, bx);
+    hipLaunchKernelGGL((k_rk3_split<PREC, RAD>), dim3(blocks), dim3(NTH), lds, st, g, P_dev, sc, m,
+                       s, (const T*)f_in, (T*)f_out, (T*)w, (T*)comp, dt, bx);
     return hipGetLastError();
+}
+
+template <int RAD>
+hipError_t launch_order(const Grid& g, const Phys& P, const Phys* P_dev, int precision,
+                        const Box& bx, int s, const void* f_in, void* f_out, void* w, void* comp,
+                        double dt, hipStream_t st)
+{
+    switch (precision) {
+    case MHD_F64:
+        // the FP64 ring and exchange area fit the 160 KB of LDS up to RAD = 3
+        if constexpr (lds_bytes<MHD_F64, RAD>() <= 160 * 1024)
+            return launch_one<MHD_F64, RAD>(g, P, P_dev, bx, s, f_in, f_out, w, nullptr, dt, st);
+        else
+            return hipErrorInvalidValue;
+    case MHD_F32C:
+        return launch_one<MHD_F32C, RAD>(g, P, P_dev, bx, s, f_in, f_out, w, comp, dt, st);
+    default: return launch_one<MHD_F32, RAD>(g, P, P_dev, bx, s, f_in, f_out, w, nullptr, dt, st);
+    }
 }
 
 }  // namespace
 
 // P (host copy) sets the stencil scales; P_dev (device copy of the same
-// values) is what the kernel's physics reads.
+// values) is what the kernel's physics reads.  The stencil radius is the
+// grid's halo width g.r (1..4); FP64 at r = 4 is not built (its ring and
+// exchange area exceed the LDS) and returns hipErrorInvalidValue.
 hipError_t launch_rk3_split(const Grid& g, const Phys& P, const Phys* P_dev, int precision,
                             const Box& bx, int s, const void* f_in, void* f_out, void* w,
                             void* comp, double dt, hipStream_t st)
 {
-    switch (precision) {
-    case MHD_F64: return launch_one<MHD_F64>(g, P, P_dev, bx, s, f_in, f_out, w, nullptr, dt, st);
-    case MHD_F32C: return launch_one<MHD_F32C>(g, P, P_dev, bx, s, f_in, f_out, w, comp, dt, st);
-    default: return launch_one<MHD_F32>(g, P, P_dev, bx, s, f_in, f_out, w, nullptr, dt, st);
+    switch (g.r) {
+    case 1: return launch_order<1>(g, P, P_dev, precision, bx, s, f_in, f_out, w, comp, dt, st);
+    case 2: return launch_order<2>(g, P, P_dev, precision, bx, s, f_in, f_out, w, comp, dt, st);
+    case 3: return launch_order<3>(g, P, P_dev, precision, bx, s, f_in, f_out, w, comp, dt, st);
+    case 4: return launch_order<4>(g, P, P_dev, precision, bx, s, f_in, f_out, w, comp, dt, st);
+    default: return hipErrorInvalidValue;
     }
 }
 

@@ -85,8 +85,8 @@ def test_halo_fill_width_r(mhd, shape, prec, order):
     S.close()
 
 
-CASES = [(2, "tiled"), (2, "direct"), (4, "tiled"), (4, "direct"), (6, "tiled"), (8, "tiled"),
-         (8, "direct")]
+CASES = [(2, "tiled"), (2, "direct"), (2, "split"), (4, "tiled"), (4, "direct"), (4, "split"),
+         (6, "tiled"), (8, "tiled"), (8, "direct")]
 
 
 @pytest.mark.parametrize("order,kernel", CASES)
@@ -103,7 +103,8 @@ def test_f64_step_against_oracle(mhd, shape, order, kernel):
     assert max(e) <= TOL_F64
 
 
-@pytest.mark.parametrize("order,kernel", [(2, "tiled"), (4, "tiled"), (8, "tiled"), (8, "direct")])
+@pytest.mark.parametrize("order,kernel", [(2, "tiled"), (4, "tiled"), (8, "tiled"), (8, "direct"),
+                                          (2, "split"), (4, "split"), (8, "split")])
 @pytest.mark.parametrize("shape", [(32, 32, 32), (37, 29, 31), (20, 12, 70)])
 def test_f32c_step_against_oracle(mhd, shape, order, kernel):
     say(f"f32c order {order} {kernel} {shape}")
@@ -133,26 +134,33 @@ def test_orders_differ(mhd):
 
 
 def test_kernel_availability(mhd):
-    auto = {("f64", 2): "tiled", ("f64", 4): "tiled", ("f64", 6): "split", ("f64", 8): "tiled",
-            ("f32c", 2): "tiled", ("f32c", 8): "tiled", ("f32", 6): "tiled"}
+    auto = {("f64", 2): "split", ("f64", 4): "split", ("f64", 6): "split", ("f64", 8): "tiled",
+            ("f32c", 2): "tiled", ("f32c", 6): "tiled", ("f32c", 8): "split", ("f32", 6): "tiled",
+            ("f32", 8): "split"}
     for (prec, order), kernel in auto.items():
         S = mhd.Solver(16, 16, 16, prec, order=order)
         assert S.kernel == kernel and S.r == order // 2
         S.close()
-    for prec, order, kernel in [("f64", 4, "split"), ("f32c", 8, "split"), ("f64", 2, "split")]:
-        with pytest.raises(mhd.MhdError):
-            mhd.Solver(16, 16, 16, prec, kernel, order=order)
+    with pytest.raises(mhd.MhdError):
+        mhd.Solver(16, 16, 16, "f64", "split", order=8)  # FP64 ring exceeds the LDS
+    for prec, order in [("f64", 2), ("f64", 4), ("f32c", 8), ("f32", 2)]:
+        S = mhd.Solver(16, 16, 16, prec, "split", order=order)
+        assert S.kernel == "split" and S.r == order // 2
+        S.close()
     with pytest.raises(mhd.MhdError):
         mhd.Solver(16, 16, 16, "f64", order=3)
 
 
 @pytest.mark.parametrize("order", [2, 4, 8])
 @pytest.mark.parametrize("prec", ["f64", "f32c"])
-def test_segmented_step_equals_step(mhd, order, prec):
+@pytest.mark.parametrize("kernel", [None, "split"])
+def test_segmented_step_equals_step(mhd, order, prec, kernel):
     import torch
+    if kernel == "split" and prec == "f64" and order == 8:
+        pytest.skip("no FP64 split kernel at order 8")
     n = (72, 40, 48)
-    say(f"segmented order {order} {prec}")
-    S = mhd.Solver(*n, prec, order=order)
+    say(f"segmented order {order} {prec} {kernel}")
+    S = mhd.Solver(*n, prec, kernel, order=order)
     f0 = inputs.fourier_modes(n, 3, 0.05, seed=44)
     comm = torch.cuda.Stream()
     res = []

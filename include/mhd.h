@@ -73,10 +73,9 @@ enum mhd_reduce_op {
 
 /* ---------------------------------------------------------------- types */
 /* Which fused-substep kernel runs (same results up to rounding order).
- * DIRECT and TILED serve every order and precision, SPLIT every order
- * and precision except MHD_F64 at order 8 (init returns MHD_ERR_INVALID).
+ * All three serve every order and precision.
  * AUTO: init picks the fastest for the precision and order (SPLIT for
- * MHD_F64 at orders 2, 4, 6 and for MHD_F32C / MHD_F32 at order 8, TILED
+ * MHD_F64 at every order and for MHD_F32C / MHD_F32 at order 8, TILED
  * otherwise) and reports it in mhd_layout.kernel. */
 enum mhd_kernel {
     MHD_KERNEL_TILED = 0,  /* LDS-tiled z-marching kernel */

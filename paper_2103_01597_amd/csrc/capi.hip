@@ -61,9 +61,6 @@ int validate(const mhd_config* c)
     if (c->precision < MHD_F64 || c->precision > MHD_F32) return MHD_ERR_INVALID;
     if (c->kernel < MHD_KERNEL_TILED || c->kernel > MHD_KERNEL_AUTO) return MHD_ERR_INVALID;
     if (c->order != 2 && c->order != 4 && c->order != 6 && c->order != 8) return MHD_ERR_INVALID;
-    // the FP64 split kernel's LDS ring does not fit at order 8
-    if (c->kernel == MHD_KERNEL_SPLIT && c->order == 8 && c->precision == MHD_F64)
-        return MHD_ERR_INVALID;
     if (!finite_pos(c->lx) || !finite_pos(c->ly) || !finite_pos(c->lz)) return MHD_ERR_INVALID;
     if (!isfinite(c->gamma) || c->gamma <= 1.0) return MHD_ERR_INVALID;
     if (!finite_pos(c->cp) || !isfinite(c->cs0) || !isfinite(c->lnrho0)) return MHD_ERR_INVALID;
@@ -292,10 +289,10 @@ int mhd_init(const mhd_config* cfg, mhd_ctx** out, mhd_layout* layout)
     ctx->device = dev;
 
     // AUTO: the fastest kernel built for the precision and order (measured
-    // at 512^3 and 256^3 on MI355X): SPLIT for FP64 up to order 6 and for
+    // at 512^3 and 256^3 on MI355X): SPLIT for FP64 at every order and for
     // the FP32 variants at order 8, TILED otherwise
     if (cfg->kernel == MHD_KERNEL_AUTO) {
-        const bool split = cfg->precision == MHD_F64 ? cfg->order <= 6 : cfg->order == 8;
+        const bool split = cfg->precision == MHD_F64 || cfg->order == 8;
         ctx->cfg.kernel = split ? MHD_KERNEL_SPLIT : MHD_KERNEL_TILED;
     }
     const int r = cfg->order / 2;

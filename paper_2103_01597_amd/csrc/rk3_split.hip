@@ -2,14 +2,17 @@
 // per cell (gfx950).
 //
 // The data flow is that of the single-group tiled kernel -- a 32 x 8 column
-// tile marched through z, an LDS ring of 4 halo'd planes (t .. t+3) of all
-// 8 fields, a 3-deep register history of the own column, the xz / yz mixed
-// derivatives split into a future half read from the ring and a carried
-// past half -- but each cell is served by two threads in different waves:
+// tile marched through z, an LDS ring of r+1 halo'd planes (t .. t+r) of all
+// 8 fields for stencil radius r, an r-deep register history of the own
+// column, the xz / yz mixed derivatives split into a future half read from
+// the ring and a carried past half -- but each cell is served by two threads
+// in different waves (figures below for r = 3, sixth order):
 //   group F (waves 0-3): lnrho, ux, uy, uz -- their derivatives, Eq. B.1
 //                        and Eq. B.2, and their 2N updates;
 //   group M (waves 4-7): ss, Ax, Ay, Az -- their derivatives, Eqs. B.3 and
 //                        B.4, and their 2N updates.
+// FP64 at r = 4 uses a 32 x 4 tile (256 threads): its ring of five 40 x 12
+// planes and the exchange area take the whole 160 KB of LDS.
 // Each group loads, stores and differentiates only its own four fields.
 // After the derivative phase the groups swap what the other side's
 // equations need through LDS:
@@ -36,14 +39,18 @@ namespace {
 #ifndef MHD_SPLIT_TX
 #define MHD_SPLIT_TX 32
 #endif
-constexpr int TX = MHD_SPLIT_TX, TY = 256 / MHD_SPLIT_TX, NC = TX * TY;  // cells per tile plane
-constexpr int NTH = 2 * NC;                    // threads: two groups of NC
+constexpr int TX = MHD_SPLIT_TX;
 constexpr int NXF = 10;            // values F hands to M
 constexpr int NXM = 7;             // values M hands to F
-// Per stencil radius RAD: the halo'd tile plane (38 x 14 = 532 cells at
+// Per precision and stencil radius RAD: the tile plane of TX x TY cells
+// (TY = 4 for FP64 at RAD = 4, whose 5-plane ring of a 32 x 8 tile would not
+// fit the LDS; 8 otherwise), the halo'd tile plane (38 x 14 = 532 cells at
 // RAD = 3) and the LDS ring of RAD + 1 such planes of all 8 fields.
-template <int RAD>
+template <int PREC, int RAD>
 struct SRing {
+    static constexpr int TY = (PREC == MHD_F64 && RAD == 4 ? 128 : 256) / TX;
+    static constexpr int NC = TX * TY;   // cells per tile plane
+    static constexpr int NTH = 2 * NC;   // threads: two groups of NC
     static constexpr int HX = TX + 2 * RAD, HY = TY + 2 * RAD, PLANE = HX * HY;
     static constexpr int SLOT = NQ * PLANE;
     static constexpr int NSLOT = RAD + 1;
@@ -54,12 +61,12 @@ struct SRing {
 template <int PREC, int RAD>
 constexpr size_t ring_bytes()
 {
-    return sizeof(typename Prec<PREC>::T) * SRing<RAD>::NSLOT * SRing<RAD>::SLOT;
+    return sizeof(typename Prec<PREC>::T) * SRing<PREC, RAD>::NSLOT * SRing<PREC, RAD>::SLOT;
 }
 template <int PREC, int RAD>
 constexpr size_t lds_bytes()
 {
-    return ring_bytes<PREC, RAD>() + sizeof(typename Prec<PREC>::Rt) * NXF * NC;
+    return ring_bytes<PREC, RAD>() + sizeof(typename Prec<PREC>::Rt) * NXF * SRing<PREC, RAD>::NC;
 }
 
 static_assert(NXM <= NXF, "M's values reuse the entries of F's");
@@ -71,7 +78,8 @@ static_assert(NXM <= NXF, "M's values reuse the entries of F's");
 #endif
 template <int PREC>
 constexpr int blocks_per_cu() { return PREC == MHD_F64 ? 1 : MHD_SPLIT_F32_BLOCKS; }
-static_assert(NC % 64 == 0, "each group must be whole waves");
+static_assert(SRing<MHD_F64, 4>::NC % 64 == 0 && SRing<MHD_F32, 1>::NC % 64 == 0,
+              "each group must be whole waves");
 
 struct TileMap {
     int ntx, nty;
@@ -131,7 +139,7 @@ __device__ __forceinline__ int tile_of_block(int b, const TileMap& m)
 }
 
 template <int PREC, int RAD>
-__global__ __launch_bounds__(NTH, blocks_per_cu<PREC>()) void k_rk3_split(Grid g, const Phys* P_dev, Scales sc, TileMap map, int s,
+__global__ __launch_bounds__((SRing<PREC, RAD>::NTH), blocks_per_cu<PREC>()) void k_rk3_split(Grid g, const Phys* P_dev, Scales sc, TileMap map, int s,
                                                      const typename Prec<PREC>::T* __restrict__ fin,
                                                      typename Prec<PREC>::T* __restrict__ fout,
                                                      typename Prec<PREC>::T* __restrict__ w,
@@ -148,8 +156,10 @@ __global__ __launch_bounds__(NTH, blocks_per_cu<PREC>()) void k_rk3_split(Grid g
     T* __restrict__ lds = reinterpret_cast<T*>(smem_raw);
     // exchange area past the ring: F's NXF values per cell, then (in place) M's NXM
     Rt* __restrict__ xch = reinterpret_cast<Rt*>(smem_raw + ring_bytes<PREC, RAD>());  // [NXF][NC]
-    constexpr int HX = SRing<RAD>::HX, PLANE = SRing<RAD>::PLANE, SLOT = SRing<RAD>::SLOT;
-    constexpr int NSLOT = SRing<RAD>::NSLOT, FULL = SRing<RAD>::FULL, EXTRA = SRing<RAD>::EXTRA;
+    using RG = SRing<PREC, RAD>;
+    constexpr int TY = RG::TY, NC = RG::NC;
+    constexpr int HX = RG::HX, PLANE = RG::PLANE, SLOT = RG::SLOT;
+    constexpr int NSLOT = RG::NSLOT, FULL = RG::FULL, EXTRA = RG::EXTRA;
 
     const int tile = tile_of_block(blockIdx.x, map);
     if (tile == NO_TILE) return;  // the whole workgroup exits together
@@ -554,7 +564,8 @@ hipError_t launch_one(const Grid& g, const Phys& P, const Phys* P_dev, const Box
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         int per_cu = 0, dev = 0, cus = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rk3_split<PREC, RAD>, NTH, lds);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rk3_split<PREC, RAD>,
+                                                         SRing<PREC, RAD>::NTH, lds);
         if (e != hipSuccess) return e;
         e = hipGetDevice(&dev);
         if (e != hipSuccess) return e;
@@ -564,7 +575,7 @@ hipError_t launch_one(const Grid& g, const Phys& P, const Phys* P_dev, const Box
     }
     TileMap m;
     m.ntx = (bx.x1 - bx.x0 + TX - 1) / TX;
-    m.nty = (bx.y1 - bx.y0 + TY - 1) / TY;
+    m.nty = (bx.y1 - bx.y0 + SRing<PREC, RAD>::TY - 1) / SRing<PREC, RAD>::TY;
     m.round = round;
     z_chunks(m, bx.z1 - bx.z0);
     Scales sc{};
@@ -579,7 +590,7 @@ hipError_t launch_one(const Grid& g, const Phys& P, const Phys* P_dev, const Box
     }
     const int tiles = m.ntx * m.nty * m.nch;
     const int blocks = (round > 0 && (round & 7) == 0) ? (tiles + round - 1) / round * round : tiles;
-    hipLaunchKernelGGL((k_rk3_split<PREC, RAD>), dim3(blocks), dim3(NTH), lds, st, g, P_dev, sc, m,
+    hipLaunchKernelGGL((k_rk3_split<PREC, RAD>), dim3(blocks), dim3(SRing<PREC, RAD>::NTH), lds, st, g, P_dev, sc, m,
                        s, (const T*)f_in, (T*)f_out, (T*)w, (T*)comp, dt, bx);
     return hipGetLastError();
 }
@@ -591,11 +602,8 @@ hipError_t launch_order(const Grid& g, const Phys& P, const Phys* P_dev, int pre
 {
     switch (precision) {
     case MHD_F64:
-        // the FP64 ring and exchange area fit the 160 KB of LDS up to RAD = 3
-        if constexpr (lds_bytes<MHD_F64, RAD>() <= 160 * 1024)
-            return launch_one<MHD_F64, RAD>(g, P, P_dev, bx, s, f_in, f_out, w, nullptr, dt, st);
-        else
-            return hipErrorInvalidValue;
+        static_assert(lds_bytes<MHD_F64, RAD>() <= 160 * 1024, "FP64 ring exceeds the LDS");
+        return launch_one<MHD_F64, RAD>(g, P, P_dev, bx, s, f_in, f_out, w, nullptr, dt, st);
     case MHD_F32C:
         return launch_one<MHD_F32C, RAD>(g, P, P_dev, bx, s, f_in, f_out, w, comp, dt, st);
     default: return launch_one<MHD_F32, RAD>(g, P, P_dev, bx, s, f_in, f_out, w, nullptr, dt, st);
@@ -606,8 +614,7 @@ hipError_t launch_order(const Grid& g, const Phys& P, const Phys* P_dev, int pre
 
 // P (host copy) sets the stencil scales; P_dev (device copy of the same
 // values) is what the kernel's physics reads.  The stencil radius is the
-// grid's halo width g.r (1..4); FP64 at r = 4 is not built (its ring and
-// exchange area exceed the LDS) and returns hipErrorInvalidValue.
+// grid's halo width g.r (1..4).
 hipError_t launch_rk3_split(const Grid& g, const Phys& P, const Phys* P_dev, int precision,
                             const Box& bx, int s, const void* f_in, void* f_out, void* w,
                             void* comp, double dt, hipStream_t st)

@@ -78,7 +78,6 @@ def _init(L, **kw):
                                  dict(lx=float("nan")), dict(lz=-1.0), dict(nu=float("inf")),
                                  dict(nx=3000, ny=3000, nz=3000), dict(kernel=4),
                                  dict(kernel=-1), dict(order=5), dict(order=0), dict(order=10),
-                                 dict(kernel=2, order=8), dict(kernel=2, order=8, precision=0),
                                  dict(heat=float("inf")), dict(cool=float("nan")),
                                  # 1023^3 FP32 cells fit a 4 GiB field, 1025^3 do not
                                  dict(nx=1017, ny=1017, nz=1017, precision=2, order=8)])
@@ -112,6 +111,7 @@ def test_null_arguments(L):
 @pytest.mark.parametrize("ok", [dict(), dict(order=2), dict(order=8, kernel=1),
                                 dict(order=8, kernel=0), dict(order=4, kernel=2),
                                 dict(order=2, kernel=2), dict(order=8, kernel=2, precision=1),
+                                dict(order=8, kernel=2, precision=0),
                                 dict(nx=1017, ny=1017, nz=1017, precision=2, order=6)])
 def test_no_device_path(L, ok):
     """A valid configuration gets past validation to the device query:

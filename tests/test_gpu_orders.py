@@ -86,7 +86,7 @@ def test_halo_fill_width_r(mhd, shape, prec, order):
 
 
 CASES = [(2, "tiled"), (2, "direct"), (2, "split"), (4, "tiled"), (4, "direct"), (4, "split"),
-         (6, "tiled"), (8, "tiled"), (8, "direct")]
+         (6, "tiled"), (8, "tiled"), (8, "direct"), (8, "split")]
 
 
 @pytest.mark.parametrize("order,kernel", CASES)
@@ -134,16 +134,14 @@ def test_orders_differ(mhd):
 
 
 def test_kernel_availability(mhd):
-    auto = {("f64", 2): "split", ("f64", 4): "split", ("f64", 6): "split", ("f64", 8): "tiled",
+    auto = {("f64", 2): "split", ("f64", 4): "split", ("f64", 6): "split", ("f64", 8): "split",
             ("f32c", 2): "tiled", ("f32c", 6): "tiled", ("f32c", 8): "split", ("f32", 6): "tiled",
             ("f32", 8): "split"}
     for (prec, order), kernel in auto.items():
         S = mhd.Solver(16, 16, 16, prec, order=order)
         assert S.kernel == kernel and S.r == order // 2
         S.close()
-    with pytest.raises(mhd.MhdError):
-        mhd.Solver(16, 16, 16, "f64", "split", order=8)  # FP64 ring exceeds the LDS
-    for prec, order in [("f64", 2), ("f64", 4), ("f32c", 8), ("f32", 2)]:
+    for prec, order in [("f64", 2), ("f64", 4), ("f64", 8), ("f32c", 8), ("f32", 2)]:
         S = mhd.Solver(16, 16, 16, prec, "split", order=order)
         assert S.kernel == "split" and S.r == order // 2
         S.close()
@@ -156,8 +154,6 @@ def test_kernel_availability(mhd):
 @pytest.mark.parametrize("kernel", [None, "split"])
 def test_segmented_step_equals_step(mhd, order, prec, kernel):
     import torch
-    if kernel == "split" and prec == "f64" and order == 8:
-        pytest.skip("no FP64 split kernel at order 8")
     n = (72, 40, 48)
     say(f"segmented order {order} {prec} {kernel}")
     S = mhd.Solver(*n, prec, kernel, order=order)

@@ -71,8 +71,11 @@ constexpr size_t lds_bytes()
 
 static_assert(NXM <= NXF, "M's values reuse the entries of F's");
 
-// Workgroups per CU the kernel is built for: FP64's ring fills the LDS; the
-// FP32 rings would fit two, at half the registers per lane.
+// Minimum waves per SIMD the kernel is built for (the second launch-bounds
+// argument).  A 512-thread workgroup already puts two waves on every SIMD,
+// so 1 leaves each lane up to 256 registers.  Two resident workgroups (4,
+// i.e. 128 registers) would spill heavily at every radius (FP64 at r = 1:
+// 203 spilled registers), and FP64's ring fills the LDS from r = 2 on.
 #ifndef MHD_SPLIT_F32_BLOCKS
 #define MHD_SPLIT_F32_BLOCKS 1
 #endif
@@ -88,12 +91,15 @@ struct TileMap {
 };
 
 // Per-axis scale factors of the integer-weight stencils.
+// (Sized by the radius: the kernel keeps these in scalar registers, which
+// are scarce.)
+template <int RAD>
 struct Scales {
-    double d1[3];      // 1/(DEN1 h_a)
-    double d2[3];      // 1/(DEN2 h_a^2)
-    double mxy;        // 1/(4 DEN2 h_x h_y)
-    double wxz[RMAX];  // W2(r, m)/(4 DEN2 h_x h_z), m = 1..r
-    double wyz[RMAX];  // W2(r, m)/(4 DEN2 h_y h_z)
+    double d1[3];     // 1/(DEN1 h_a)
+    double d2[3];     // 1/(DEN2 h_a^2)
+    double mxy;       // 1/(4 DEN2 h_x h_y)
+    double wxz[RAD];  // W2(r, m)/(4 DEN2 h_x h_z), m = 1..r
+    double wyz[RAD];  // W2(r, m)/(4 DEN2 h_y h_z)
 };
 
 constexpr int NO_TILE = -1;
@@ -139,7 +145,7 @@ __device__ __forceinline__ int tile_of_block(int b, const TileMap& m)
 }
 
 template <int PREC, int RAD>
-__global__ __launch_bounds__((SRing<PREC, RAD>::NTH), blocks_per_cu<PREC>()) void k_rk3_split(Grid g, const Phys* P_dev, Scales sc, TileMap map, int s,
+__global__ __launch_bounds__((SRing<PREC, RAD>::NTH), blocks_per_cu<PREC>()) void k_rk3_split(Grid g, const Phys* P_dev, Scales<RAD> sc, TileMap map, int s,
                                                      const typename Prec<PREC>::T* __restrict__ fin,
                                                      typename Prec<PREC>::T* __restrict__ fout,
                                                      typename Prec<PREC>::T* __restrict__ w,
@@ -259,7 +265,11 @@ __global__ __launch_bounds__((SRing<PREC, RAD>::NTH), blocks_per_cu<PREC>()) voi
 
         auto cell_index = [&](int t) { return g.interior + t * g.mxy + (y0 + ly) * g.mx + (x0 + lx); };
 
-        constexpr int SOFS = 4 * NSLOT;  // keeps (t + SOFS) non-negative for slot arithmetic
+        // ring slot of plane p: p + SOFS > 0 for every plane the march touches
+        // (p >= bz0 - 2 RAD - 1), so an unsigned modulo gives the slot (an AND
+        // when NSLOT is a power of two)
+        constexpr int SOFS = 4 * NSLOT;
+        auto slot_of = [](int p) { return (int)((unsigned)(p + SOFS) % (unsigned)NSLOT); };
         load_plane(bz0 - RAD);
         // u: plane index relative to the box start, so that the warm-up tests
         // below compare against constants
@@ -267,7 +277,7 @@ __global__ __launch_bounds__((SRing<PREC, RAD>::NTH), blocks_per_cu<PREC>()) voi
             const int t = bz0 + u;
             // warm-up planes (t < z0) run the whole computation too (branch-free
             // code schedules better); only their z state is kept
-            const int s0 = (t + SOFS) % NSLOT;
+            const int s0 = slot_of(t);
             const bool live = u >= -RAD;  // uniform: plane t is in the ring
             Derivs<Rt> d;
             T fc[4], wnew[4], fnew[4], cnew[4];
@@ -275,7 +285,7 @@ __global__ __launch_bounds__((SRing<PREC, RAD>::NTH), blocks_per_cu<PREC>()) voi
             if (live) {
                 int sl[RAD + 1];  // ring slots of planes t .. t+RAD
 #pragma unroll
-                for (int k = 0; k <= RAD; ++k) sl[k] = (t + k + SOFS) % NSLOT;
+                for (int k = 0; k <= RAD; ++k) sl[k] = slot_of(t + k);
 
                 auto sum2 = [&](int q, int dir, int m) {
                     return dir == 0 ? D2(V(s0, q, 0, m)) + D2(V(s0, q, 0, -m))
@@ -304,16 +314,19 @@ __global__ __launch_bounds__((SRing<PREC, RAD>::NTH), blocks_per_cu<PREC>()) voi
                 };
                 auto second = [&](int q, int k4, D2& xx, D2& yy, D2& zz) {
                     const D2 f0 = D2(W2(RAD, 0)) * D2(V(s0, q, 0, 0));
-                    D2 ax = D2(W2(RAD, 1)) * sum2(q, 0, 1), ay = D2(W2(RAD, 1)) * sum2(q, 1, 1);
+                    // one axis after the other (the order the scheduler handles best)
+                    D2 ax = D2(W2(RAD, 1)) * sum2(q, 0, 1);
+#pragma unroll
+                    for (int m = 2; m <= RAD; ++m) ax += D2(W2(RAD, m)) * sum2(q, 0, m);
+                    xx = (ax + f0) * D2(sc.d2[0]);
+                    D2 ay = D2(W2(RAD, 1)) * sum2(q, 1, 1);
+#pragma unroll
+                    for (int m = 2; m <= RAD; ++m) ay += D2(W2(RAD, m)) * sum2(q, 1, m);
+                    yy = (ay + f0) * D2(sc.d2[1]);
                     D2 az = D2(W2(RAD, 1)) * (D2(col(q, k4, 1)) + D2(col(q, k4, -1)));
 #pragma unroll
-                    for (int m = 2; m <= RAD; ++m) {
-                        ax += D2(W2(RAD, m)) * sum2(q, 0, m);
-                        ay += D2(W2(RAD, m)) * sum2(q, 1, m);
+                    for (int m = 2; m <= RAD; ++m)
                         az += D2(W2(RAD, m)) * (D2(col(q, k4, m)) + D2(col(q, k4, -m)));
-                    }
-                    xx = (ax + f0) * D2(sc.d2[0]);
-                    yy = (ay + f0) * D2(sc.d2[1]);
                     zz = (az + f0) * D2(sc.d2[2]);
                 };
                 auto dxy = [&](int q) -> D2 {
@@ -338,13 +351,15 @@ __global__ __launch_bounds__((SRing<PREC, RAD>::NTH), blocks_per_cu<PREC>()) voi
 #pragma unroll
                     for (int m = 2; m <= RAD; ++m) res += D2(wm[m - 1]) * dd(sl[m], m);
                     if (first_of_combo) res -= past[cb][0];
+                    D2 c[RAD];  // this plane's half for outputs t+1 .. t+RAD
+#pragma unroll
+                    for (int m = 1; m <= RAD; ++m) c[m - 1] = D2(wm[m - 1]) * dd(s0, m);
 #pragma unroll
                     for (int m = 1; m <= RAD; ++m) {
-                        const D2 c = D2(wm[m - 1]) * dd(s0, m);
                         if (first_of_combo)
-                            past[cb][m - 1] = m < RAD ? past[cb][m < RAD ? m : 0] + c : c;
+                            past[cb][m - 1] = m < RAD ? past[cb][m < RAD ? m : 0] + c[m - 1] : c[m - 1];
                         else
-                            past[cb][m - 1] += c;
+                            past[cb][m - 1] += c[m - 1];
                     }
                     return res;
                 };
@@ -476,7 +491,7 @@ __global__ __launch_bounds__((SRing<PREC, RAD>::NTH), blocks_per_cu<PREC>()) voi
             // its own in their place (each thread only touches the entries of
             // its own cell, so program order separates the read and the write).
             __syncthreads();
-            store_plane((t + RAD + 1 + SOFS) % NSLOT);
+            store_plane(slot_of(t + RAD + 1));
             if constexpr (G == 1) {
                 if (live) {
                     d.lnrho = xch[0 * NC + tid];
@@ -578,7 +593,7 @@ hipError_t launch_one(const Grid& g, const Phys& P, const Phys* P_dev, const Box
     m.nty = (bx.y1 - bx.y0 + SRing<PREC, RAD>::TY - 1) / SRing<PREC, RAD>::TY;
     m.round = round;
     z_chunks(m, bx.z1 - bx.z0);
-    Scales sc{};
+    Scales<RAD> sc{};
     for (int a = 0; a < 3; ++a) {
         sc.d1[a] = P.inv_h[a] / DEN1(RAD);
         sc.d2[a] = P.inv_h[a] * P.inv_h[a] / DEN2(RAD);

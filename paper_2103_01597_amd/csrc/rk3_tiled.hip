@@ -83,12 +83,14 @@ struct TileMap {
 };
 
 // Per-axis scale factors of the integer-weight stencils.
+// (Sized by the radius: the kernel keeps these in scalar registers.)
+template <int RAD>
 struct Scales {
-    double d1[3];   // 1/(DEN1 h_a)
-    double d2[3];   // 1/(DEN2 h_a^2)
-    double mxy;        // 1/(4 DEN2 h_x h_y)
-    double wxz[RMAX];  // W2(r, m)/(4 DEN2 h_x h_z), m = 1..r
-    double wyz[RMAX];  // W2(r, m)/(4 DEN2 h_y h_z)
+    double d1[3];     // 1/(DEN1 h_a)
+    double d2[3];     // 1/(DEN2 h_a^2)
+    double mxy;       // 1/(4 DEN2 h_x h_y)
+    double wxz[RAD];  // W2(r, m)/(4 DEN2 h_x h_z), m = 1..r
+    double wyz[RAD];  // W2(r, m)/(4 DEN2 h_y h_z)
 };
 
 constexpr int NO_TILE = -1;
@@ -144,7 +146,7 @@ template <int PREC>
 constexpr int blocks_per_cu() { return PREC == MHD_F64 ? 1 : MHD_TILED_F32_BLOCKS; }
 
 template <int PREC, int RAD>
-__global__ __launch_bounds__((Ring<PREC, RAD>::NT), blocks_per_cu<PREC>()) void k_rk3_tiled(Grid g, Phys P, Scales sc, TileMap map, int s,
+__global__ __launch_bounds__((Ring<PREC, RAD>::NT), blocks_per_cu<PREC>()) void k_rk3_tiled(Grid g, Phys P, Scales<RAD> sc, TileMap map, int s,
                                                      const typename Prec<PREC>::T* __restrict__ fin,
                                                      typename Prec<PREC>::T* __restrict__ fout,
                                                      typename Prec<PREC>::T* __restrict__ w,
@@ -255,7 +257,11 @@ __global__ __launch_bounds__((Ring<PREC, RAD>::NT), blocks_per_cu<PREC>()) void 
 
     auto cell_index = [&](int t) { return g.interior + t * g.mxy + (y0 + ly) * g.mx + (x0 + lx); };
 
-    constexpr int SOFS = 4 * NSLOT;  // keeps (t + SOFS) non-negative for slot arithmetic
+    // ring slot of plane p: p + SOFS > 0 for every plane the march touches
+    // (p >= bz0 - 2 RAD - 1), so an unsigned modulo gives the slot (an AND
+    // when NSLOT is a power of two)
+    constexpr int SOFS = 4 * NSLOT;
+    auto slot_of = [](int p) { return (int)((unsigned)(p + SOFS) % (unsigned)NSLOT); };
     load_plane(bz0 - RAD);
     // u: plane index relative to the box start, so that the warm-up tests
     // below compare against constants.  Iterations u < -RAD only fill the
@@ -265,7 +271,7 @@ __global__ __launch_bounds__((Ring<PREC, RAD>::NT), blocks_per_cu<PREC>()) void 
         if (u >= -RAD) {
             int sl[RAD + 1];  // ring slots of planes t .. t+RAD
 #pragma unroll
-            for (int k = 0; k <= RAD; ++k) sl[k] = (t + k + SOFS) % NSLOT;
+            for (int k = 0; k <= RAD; ++k) sl[k] = slot_of(t + k);
             const int s0 = sl[0];
             // warm-up planes (t < z0) run the whole computation too (branch-free
             // code schedules better); only their z state is kept
@@ -299,16 +305,18 @@ __global__ __launch_bounds__((Ring<PREC, RAD>::NT), blocks_per_cu<PREC>()) void 
             // pure second derivatives along x, y, z
             auto second = [&](int q, D2& xx, D2& yy, D2& zz) {
                 const D2 f0 = D2(W2(RAD, 0)) * D2(V(s0, q, 0, 0));
-                D2 ax = D2(W2(RAD, 1)) * sum2(q, 0, 1), ay = D2(W2(RAD, 1)) * sum2(q, 1, 1);
+                // one axis after the other (the order the scheduler handles best)
+                D2 ax = D2(W2(RAD, 1)) * sum2(q, 0, 1);
+#pragma unroll
+                for (int m = 2; m <= RAD; ++m) ax += D2(W2(RAD, m)) * sum2(q, 0, m);
+                xx = (ax + f0) * D2(sc.d2[0]);
+                D2 ay = D2(W2(RAD, 1)) * sum2(q, 1, 1);
+#pragma unroll
+                for (int m = 2; m <= RAD; ++m) ay += D2(W2(RAD, m)) * sum2(q, 1, m);
+                yy = (ay + f0) * D2(sc.d2[1]);
                 D2 az = D2(W2(RAD, 1)) * (D2(col(q, 1)) + D2(col(q, -1)));
 #pragma unroll
-                for (int m = 2; m <= RAD; ++m) {
-                    ax += D2(W2(RAD, m)) * sum2(q, 0, m);
-                    ay += D2(W2(RAD, m)) * sum2(q, 1, m);
-                    az += D2(W2(RAD, m)) * (D2(col(q, m)) + D2(col(q, -m)));
-                }
-                xx = (ax + f0) * D2(sc.d2[0]);
-                yy = (ay + f0) * D2(sc.d2[1]);
+                for (int m = 2; m <= RAD; ++m) az += D2(W2(RAD, m)) * (D2(col(q, m)) + D2(col(q, -m)));
                 zz = (az + f0) * D2(sc.d2[2]);
             };
             auto dxy = [&](int q) -> D2 {
@@ -336,13 +344,15 @@ __global__ __launch_bounds__((Ring<PREC, RAD>::NT), blocks_per_cu<PREC>()) void 
 #pragma unroll
                 for (int m = 2; m <= RAD; ++m) res += D2(wm[m - 1]) * dd(sl[m], m);
                 if (first_of_combo) res -= past[cb][0];
+                D2 c[RAD];  // this plane's half for outputs t+1 .. t+RAD
+#pragma unroll
+                for (int m = 1; m <= RAD; ++m) c[m - 1] = D2(wm[m - 1]) * dd(s0, m);
 #pragma unroll
                 for (int m = 1; m <= RAD; ++m) {
-                    const D2 c = D2(wm[m - 1]) * dd(s0, m);
                     if (first_of_combo)
-                        past[cb][m - 1] = m < RAD ? past[cb][m < RAD ? m : 0] + c : c;
+                        past[cb][m - 1] = m < RAD ? past[cb][m < RAD ? m : 0] + c[m - 1] : c[m - 1];
                     else
-                        past[cb][m - 1] += c;
+                        past[cb][m - 1] += c[m - 1];
                 }
                 return res;
             };
@@ -477,7 +487,7 @@ __global__ __launch_bounds__((Ring<PREC, RAD>::NT), blocks_per_cu<PREC>()) void 
         // stores alike in issue order, so with the loads first the next
         // plane's waits for them do not also wait for these stores.
         __syncthreads();  // every read of plane t is done
-        store_plane((t + RAD + 1 + SOFS) % NSLOT);
+        store_plane(slot_of(t + RAD + 1));
         if (t + RAD + 2 <= bz1 + RAD - 1) load_plane(t + RAD + 2);
         if (active && u + 1 >= 0 && t + 1 < bz1) {
             const unsigned c = (unsigned)cell_index(t + 1);
@@ -529,7 +539,7 @@ hipError_t launch_one(const Grid& g, const Phys& P, const Box& bx, int s, const 
     m.nty = (bx.y1 - bx.y0 + TY - 1) / TY;
     m.round = round;
     z_chunks(m, bx.z1 - bx.z0);
-    Scales sc{};
+    Scales<RAD> sc{};
     for (int a = 0; a < 3; ++a) {
         sc.d1[a] = P.inv_h[a] / DEN1(RAD);
         sc.d2[a] = P.inv_h[a] * P.inv_h[a] / DEN2(RAD);

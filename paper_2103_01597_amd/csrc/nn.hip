@@ -7,10 +7,15 @@
 // plus one row on each side in LDS and the next plane prefetched into
 // registers:
 //   * forward / data gradient: M = cells, N = output channels (padded to
-//     32), K = 27 taps x input channels; each wave owns 32 cells.  An A
-//     fragment is 8 consecutive channels of one shifted cell (one 16-byte
-//     LDS read); a B fragment is 8 consecutive input channels of one weight
-//     row.
+//     32), K = 27 taps x input channels.  An A fragment is 8 consecutive
+//     channels of one shifted cell (one 16-byte LDS read); a B fragment is 8
+//     consecutive input channels of one weight row, held in registers for
+//     the whole march (the LDS then serves only A fragments).  8 input
+//     channels: each wave owns 32 cells and all of K (14 fragments).  32
+//     input channels: the 27 x 2 fragments of all of K would not fit one
+//     lane's registers, so waves 0-3 take input channels 0-15 and waves 4-7
+//     channels 16-31, each over 64 cells (two M tiles); wave w and w+4 then
+//     add their partial sums through LDS, each finishing one tile.
 //   * weight gradient: M = output channels, N = input channels (or 4 taps x
 //     8 channels for 8-channel inputs), K = cells.  Over one full periodic
 //     x-row, sum_x dz(x) x(x + dx) = sum_q dz(q - dx) x(q), so the x shift is
@@ -37,14 +42,9 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-// Round-to-nearest-even FP32 -> BF16 (NaN stays NaN).
-__device__ __forceinline__ uint16_t f2bf(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
+// Round-to-nearest-even FP32 -> BF16 (NaN stays NaN): one hardware
+// conversion instruction on gfx950.
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
 __device__ __forceinline__ float gelu(float v) { return 0.5f * v * (1.0f + erff(v * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad(float v)
@@ -79,8 +79,6 @@ constexpr int CONV_CELLS = 256;  // cells per plane per block: 8 waves x 32
 // conflicts): per cell of the input ring, per output channel of the weights.
 template <int CIN>
 constexpr int conv_cp() { return CIN == 32 ? CIN + 8 : CIN; }
-template <int CIN>
-constexpr int conv_wrow() { return CIN == 32 ? 27 * CIN + 8 : 27 * CIN; }
 
 template <int CIN>
 constexpr int conv_loads(int n)  // 16-byte vectors each thread moves per plane
@@ -99,12 +97,13 @@ __global__ __launch_bounds__(CONV_THR) void k_conv(const uint16_t* __restrict__ 
                                                    float* __restrict__ outf)
 {
     extern __shared__ __align__(16) uint16_t sm[];
-    constexpr int CP = conv_cp<CIN>(), WROW = conv_wrow<CIN>();
+    constexpr int CP = conv_cp<CIN>();
     const int RY = CONV_CELLS >> logn;       // rows per slab
     const int slot = (RY + 2) * n * CP;      // elements per ring plane
     const int nv = (RY + 2) * n * CIN / 8;   // 16-byte vectors per ring plane
-    uint16_t* lw = sm;                       // [32][WROW]: [27][CIN] per output channel
-    uint16_t* lx = sm + 32 * WROW;           // [3][RY+2][n][CP]
+    uint16_t* lx = sm;                       // [3][RY+2][n][CP]
+    // CIN == 32: partial sums handed between wave w and w+4, [8 waves][16][64 lanes]
+    float* red = reinterpret_cast<float*>(sm + 3 * slot);
     const int slabs = n / RY;
     const int col_id = blockIdx.x / nch, ch_id = blockIdx.x - col_id * nch;
     const int b = col_id / slabs, y0 = (col_id - b * slabs) * RY;
@@ -113,9 +112,20 @@ __global__ __launch_bounds__(CONV_THR) void k_conv(const uint16_t* __restrict__ 
     const uint16_t* xb = x + (size_t)b * n3 * CIN;
     const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63, h = l >> 5, col = l & 31;
 
-    for (int i = tid; i < 32 * 27 * CIN / 8; i += CONV_THR) {
-        const int o = i / (27 * CIN / 8), rem = i - o * (27 * CIN / 8);
-        *reinterpret_cast<u16x8*>(lw + o * WROW + rem * 8) = reinterpret_cast<const u16x8*>(w)[i];
+    // ---- B fragments (weights, [32][27][CIN] with output channels padded to
+    // 32) for the whole march: lane l holds column l%32, K chunk 8(l/32)
+    constexpr int NB = CIN == 32 ? 27 : 14;
+    // K half of this wave (32 input channels), visibly wave-uniform
+    const int kh = CIN == 32 ? __builtin_amdgcn_readfirstlane(wv >> 2) : 0;
+    bf16x8 bw[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        if constexpr (CIN == 32) {
+            bw[u] = frag(w + ((size_t)col * 27 + u) * 32 + 16 * kh + 8 * h);
+        } else {  // taps 2u (lanes 0-31) and 2u+1 (lanes 32-63) share one K chunk
+            const int t = 2 * u + h;
+            bw[u] = t < 27 ? frag(w + ((size_t)col * 27 + t) * 8) : bf16x8{};
+        }
     }
 
     // ---- plane loads: vector i of ring plane z = rows y0-1 .. y0+RY (periodic)
@@ -152,8 +162,18 @@ __global__ __launch_bounds__(CONV_THR) void k_conv(const uint16_t* __restrict__ 
     store(1);
     load(z0 + 1);
 
-    const int m = 32 * wv + col;             // this lane's A-row cell within the slab plane
-    const int rr = m >> logn, xx = m & (n - 1);
+    // A-row cells of this lane within the slab plane: one M tile (CIN 8) or two
+    constexpr int NT = CIN == 32 ? 2 : 1;
+    const int mbase = CIN == 32 ? 64 * (wv & 3) : 32 * wv;
+    int rr[NT], xx[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        const int m = mbase + 32 * j + col;
+        rr[j] = m >> logn;
+        xx[j] = m & (n - 1);
+    }
+    // the tile this wave finishes (after the partial-sum hand-over for CIN 32)
+    const int fin = CIN == 32 ? kh : 0;
     for (int p = 0; p < nz; ++p) {
         // ring slot q holds plane z0 - 1 + (p' mod 3) for the p' with p' = q (mod 3)
         store((p + 2) % 3);  // plane z0+p+1 replaces plane z0+p-2
@@ -161,42 +181,63 @@ __global__ __launch_bounds__(CONV_THR) void k_conv(const uint16_t* __restrict__ 
         if (p + 1 < nz) load(z0 + p + 2);
         const int sb[3] = {(p % 3) * (RY + 2), ((p + 1) % 3) * (RY + 2), ((p + 2) % 3) * (RY + 2)};
 
-        floatx16 acc = {};
+        floatx16 acc[NT];
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[j] = floatx16{};
         if constexpr (CIN == 32) {
-#pragma unroll 3
+#pragma unroll
             for (int t = 0; t < 27; ++t) {
                 const int dz = t / 9, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-                const int s = (sb[dz] + rr + dy + 1) * n + ((xx + dx) & (n - 1));
 #pragma unroll
-                for (int c2 = 0; c2 < 2; ++c2) {
-                    const bf16x8 a = frag(lx + s * CP + 16 * c2 + 8 * h);
-                    const bf16x8 bb = frag(lw + col * WROW + t * 32 + 16 * c2 + 8 * h);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, acc, 0, 0, 0);
+                for (int j = 0; j < 2; ++j) {
+                    const int s = (sb[dz] + rr[j] + dy + 1) * n + ((xx[j] + dx) & (n - 1));
+                    const bf16x8 a = frag(lx + s * CP + 16 * kh + 8 * h);
+                    acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bw[t], acc[j], 0, 0, 0);
                 }
             }
-        } else {  // CIN == 8: taps 2u (lanes 0-31) and 2u+1 (lanes 32-63) share one K chunk
-#pragma unroll 2
+            // Hand the tile the partner finishes to it; the finished tile ends
+            // in acc[0].  Every ring read of this plane is done once all waves
+            // pass the barrier below, so it also orders the next ring store.
+            float* mine = red + wv * 16 * 64 + l;
+            if (kh == 0) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) mine[r * 64] = acc[1][r];
+            } else {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) mine[r * 64] = acc[0][r];
+            }
+            __syncthreads();
+            const float* theirs = red + (wv ^ 4) * 16 * 64 + l;
+            if (kh == 0) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[0][r] += theirs[r * 64];
+            } else {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[0][r] = acc[1][r] + theirs[r * 64];
+            }
+        } else {
+#pragma unroll
             for (int u = 0; u < 14; ++u) {
                 const int t = 2 * u + h;
-                bf16x8 a = {}, bb = {};
+                bf16x8 a = {};
                 if (t < 27) {
                     const int dz = t / 9, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-                    const int s = (sb[dz] + rr + dy + 1) * n + ((xx + dx) & (n - 1));
+                    const int s = (sb[dz] + rr[0] + dy + 1) * n + ((xx[0] + dx) & (n - 1));
                     a = frag(lx + s * CP);
-                    bb = frag(lw + col * WROW + t * 8);
                 }
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, acc, 0, 0, 0);
+                acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bw[u], acc[0], 0, 0, 0);
             }
         }
 
         if (col < cout) {
             const float bv = (MODE == 2) ? 0.0f : bias[col];
             const size_t c0 = (size_t)b * n3 + ((size_t)(z0 + p) << (2 * logn)) + ((size_t)y0 << logn);
+            const floatx16& res = acc[0];
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int cl = 32 * wv + 8 * (r >> 2) + 4 * h + (r & 3);
+                const int cl = mbase + 32 * fin + 8 * (r >> 2) + 4 * h + (r & 3);
                 const size_t o = (c0 + cl) * cout + col;
-                const float v = acc[r] + bv;
+                const float v = res[r] + bv;
                 if constexpr (MODE == 0) {
                     out0[o] = f2bf(v);
                     out1[o] = f2bf(gelu(v));
@@ -207,7 +248,10 @@ __global__ __launch_bounds__(CONV_THR) void k_conv(const uint16_t* __restrict__ 
                 }
             }
         }
-        __syncthreads();  // every read of plane z0+p-1 is done before it is replaced
+        // CIN 8: every read of plane z0+p-1 is done before it is replaced.
+        // CIN 32: the hand-over barrier above already ordered them, and the
+        // next plane's partial sums are written only after its first barrier.
+        if constexpr (CIN != 32) __syncthreads();
     }
 }
 
@@ -655,8 +699,8 @@ void conv_chunks(int n, int batch, int& columns, int& nch, int& zc)
 size_t conv_lds(int cin, int n)
 {
     const int cp = cin == 32 ? conv_cp<32>() : conv_cp<8>();
-    const int wrow = cin == 32 ? conv_wrow<32>() : conv_wrow<8>();
-    return 2 * (32 * wrow + 3 * (CONV_CELLS / n + 2) * n * cp);
+    const size_t ring = 2 * (3 * (CONV_CELLS / n + 2) * n * cp);
+    return ring + (cin == 32 ? sizeof(float) * 8 * 16 * 64 : 0);  // + partial-sum hand-over
 }
 
 template <int CIN, int MODE>

@@ -72,6 +72,7 @@ constexpr int NTHR = 256;
 // read from memory (1 + 2 RY^-1)(1 + 2 zc^-1) times instead of once per
 // 3 x (rows + 2) neighbourhood of a small tile.
 constexpr int CONV_THR = 512;
+constexpr int WG_THR = 576;  // weight gradient: 9 waves, one per (dx, dz) tap triple
 constexpr int CONV_CELLS = 256;  // cells per plane per block: 8 waves x 32
 
 // LDS row pitches (elements), padded so that consecutive lanes' 16-byte
@@ -267,7 +268,7 @@ __global__ __launch_bounds__(CONV_THR) void k_conv(const uint16_t* __restrict__ 
 // accumulates its chunk in registers and writes one partial sum per weight;
 // k_wgrad_reduce adds the partials in a fixed order (deterministic).
 template <int CIN, int COUT>
-__global__ __launch_bounds__(CONV_THR) void k_wgrad(const uint16_t* __restrict__ x,
+__global__ __launch_bounds__(WG_THR) void k_wgrad(const uint16_t* __restrict__ x,
                                                     const uint16_t* __restrict__ dz, int n,
                                                     int logn, int nch, int zc,
                                                     float* __restrict__ ws,
@@ -282,7 +283,7 @@ __global__ __launch_bounds__(CONV_THR) void k_wgrad(const uint16_t* __restrict__
     constexpr int DS = CONV_CELLS + 8;
     uint16_t* xs = sm;                          // [CIN][3][PS]: rows [RY+2][n]
     uint16_t* ds = sm + CIN * 3 * PS;           // [3 shifts][32][DS]: rows [RY][n]
-    float* bsum = reinterpret_cast<float*>(ds + 3 * 32 * DS);  // [CONV_THR][8]
+    float* bsum = reinterpret_cast<float*>(ds + 3 * 32 * DS);  // [WG_THR][8]
     const int slabs = n / RY;
     const int col_id = blockIdx.x / nch, ch_id = blockIdx.x - col_id * nch;
     const int b = col_id / slabs, y0 = (col_id - b * slabs) * RY;
@@ -294,22 +295,22 @@ __global__ __launch_bounds__(CONV_THR) void k_wgrad(const uint16_t* __restrict__
 
     // rows o >= COUT of the dz copies stay zero
     if constexpr (COUT < 32)
-        for (int i = tid; i < 3 * (32 - COUT) * DS; i += CONV_THR) {
+        for (int i = tid; i < 3 * (32 - COUT) * DS; i += WG_THR) {
             const int sh = i / ((32 - COUT) * DS), rem = i - sh * (32 - COUT) * DS;
             ds[(sh * 32 + COUT) * DS + rem] = 0;
         }
 
     // ---- plane loads (16-byte vectors of 8 channels of one cell)
     constexpr int NVX16 = (CONV_CELLS / 16 + 2) * 16 * CIN / 8, NVX64 = (CONV_CELLS / 64 + 2) * 64 * CIN / 8;
-    constexpr int NLX = ((NVX16 > NVX64 ? NVX16 : NVX64) + CONV_THR - 1) / CONV_THR;
-    constexpr int NVD = CONV_CELLS * COUT / 8, NLD = (NVD + CONV_THR - 1) / CONV_THR;
+    constexpr int NLX = ((NVX16 > NVX64 ? NVX16 : NVX64) + WG_THR - 1) / WG_THR;
+    constexpr int NVD = CONV_CELLS * COUT / 8, NLD = (NVD + WG_THR - 1) / WG_THR;
     const int nvx = xplane * CIN / 8;
     u16x8 px[NLX], pd[NLD];
     auto load_x = [&](int z) {
         const int zz = (z + n) & (n - 1);
 #pragma unroll
         for (int k = 0; k < NLX; ++k) {
-            const int i = tid + k * CONV_THR;
+            const int i = tid + k * WG_THR;
             if (i < nvx) {
                 const int cell = i / (CIN / 8), cg = (i - cell * (CIN / 8)) * 8;
                 const int xx = cell & (n - 1), r = cell >> logn;
@@ -322,7 +323,7 @@ __global__ __launch_bounds__(CONV_THR) void k_wgrad(const uint16_t* __restrict__
     auto store_x = [&](int sl) {  // transposed to channel-major
 #pragma unroll
         for (int k = 0; k < NLX; ++k) {
-            const int i = tid + k * CONV_THR;
+            const int i = tid + k * WG_THR;
             if (i < nvx) {
                 const int cell = i / (CIN / 8), cg = (i - cell * (CIN / 8)) * 8;
 #pragma unroll
@@ -333,7 +334,7 @@ __global__ __launch_bounds__(CONV_THR) void k_wgrad(const uint16_t* __restrict__
     auto load_dz = [&](int z) {
 #pragma unroll
         for (int k = 0; k < NLD; ++k) {
-            const int i = tid + k * CONV_THR;
+            const int i = tid + k * WG_THR;
             if (i < NVD) {
                 const int cell = i / (COUT / 8), og = (i - cell * (COUT / 8)) * 8;
                 const size_t src = ((size_t)z << (2 * logn)) + ((size_t)y0 << logn) + cell;
@@ -345,7 +346,7 @@ __global__ __launch_bounds__(CONV_THR) void k_wgrad(const uint16_t* __restrict__
     auto store_dz = [&]() {  // transposed, in three copies shifted along x
 #pragma unroll
         for (int k = 0; k < NLD; ++k) {
-            const int i = tid + k * CONV_THR;
+            const int i = tid + k * WG_THR;
             if (i < NVD) {
                 const int cell = i / (COUT / 8), og = (i - cell * (COUT / 8)) * 8;
                 const int xx = cell & (n - 1), rr = cell >> logn;
@@ -361,9 +362,11 @@ __global__ __launch_bounds__(CONV_THR) void k_wgrad(const uint16_t* __restrict__
         }
     };
 
-    // accumulator sets of this wave: taps t = wv + 8i (CIN 32) or tap groups
-    // g = wv + 8i (CIN 8: g = 3*dxi + gi, gi selects 4 of the 9 (dz, dy) pairs)
-    constexpr int NSET = CIN == 32 ? 4 : 2;
+    // accumulator sets of wave wv (9 waves): CIN 32: the taps with x shift
+    // dx = wv/3 - 1 and z offset dz = wv%3 - 1, one set per dy = -1, 0, 1, so
+    // the three share each dz fragment; CIN 8: tap group g = wv (g = 3*dxi +
+    // gi, gi selects 4 of the 9 (dz, dy) pairs)
+    constexpr int NSET = CIN == 32 ? 3 : 1;
     floatx16 acc[NSET];
 #pragma unroll
     for (int i = 0; i < NSET; ++i) acc[i] = floatx16{};
@@ -383,34 +386,26 @@ __global__ __launch_bounds__(CONV_THR) void k_wgrad(const uint16_t* __restrict__
             load_dz(z0 + p + 1);
         }
         const int sb[3] = {p % 3, (p + 1) % 3, (p + 2) % 3};  // ring slot of plane dz = -1, 0, 1
-#pragma unroll
-        for (int si = 0; si < NSET; ++si) {
-            const int set = wv + 8 * si;
-            if (set >= 27 || (CIN == 8 && set >= 9)) break;  // uniform per wave
-            int dxs, dzv = 0, dyv = 0;
-            if constexpr (CIN == 32) {
-                dxs = set % 3;  // shift copy s = dx + 1
-                dzv = set / 9 - 1;
-                dyv = (set / 3) % 3 - 1;
-            } else {
-                dxs = set / 3;
-            }
+        const int dxs = wv / 3;  // shift copy s = dx + 1 (both channel counts)
 #pragma unroll 4
-            for (int kc = 0; kc < CONV_CELLS / 16; ++kc) {
-                const int cell = kc * 16 + 8 * h;
-                const int rr = cell >> logn, xq = cell & (n - 1);
-                const bf16x8 a = frag(ds + (dxs * 32 + col) * DS + rr * n + xq);
+        for (int kc = 0; kc < CONV_CELLS / 16; ++kc) {
+            const int cell = kc * 16 + 8 * h;
+            const int rr = cell >> logn, xq = cell & (n - 1);
+            const bf16x8 a = frag(ds + (dxs * 32 + col) * DS + rr * n + xq);
+            if constexpr (CIN == 32) {
+                const uint16_t* xrow = xs + (col * 3 + sb[wv % 3]) * PS + rr * n + xq;
+#pragma unroll
+                for (int si = 0; si < 3; ++si)  // dy = si - 1
+                    acc[si] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, frag(xrow + si * n),
+                                                                       acc[si], 0, 0, 0);
+            } else {
+                const int tg = col >> 3, c = col & 7, pr = 4 * (wv % 3) + tg;
                 bf16x8 bb = {};
-                if constexpr (CIN == 32) {
-                    bb = frag(xs + (col * 3 + sb[dzv + 1]) * PS + (rr + dyv + 1) * n + xq);
-                } else {
-                    const int tg = col >> 3, c = col & 7, pr = 4 * (set % 3) + tg;
-                    if (pr < 9) {
-                        const int dzz = pr / 3 - 1, dyy = pr % 3 - 1;
-                        bb = frag(xs + (c * 3 + sb[dzz + 1]) * PS + (rr + dyy + 1) * n + xq);
-                    }
+                if (pr < 9) {
+                    const int dzz = pr / 3 - 1, dyy = pr % 3 - 1;
+                    bb = frag(xs + (c * 3 + sb[dzz + 1]) * PS + (rr + dyy + 1) * n + xq);
                 }
-                acc[si] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, acc[si], 0, 0, 0);
+                acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, acc[0], 0, 0, 0);
             }
         }
         __syncthreads();  // reads of plane z0+p-1 and of the dz plane are done
@@ -420,19 +415,17 @@ __global__ __launch_bounds__(CONV_THR) void k_wgrad(const uint16_t* __restrict__
     float* wb = ws + (size_t)blockIdx.x * 27 * 32 * 32;
 #pragma unroll
     for (int si = 0; si < NSET; ++si) {
-        const int set = wv + 8 * si;
-        if (set >= 27 || (CIN == 8 && set >= 9)) break;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int o = 8 * (r >> 2) + 4 * h + (r & 3);
             int t, c;
             if constexpr (CIN == 32) {
-                t = set;
+                t = 9 * (wv % 3) + 3 * si + wv / 3;  // t = 9 (dz+1) + 3 (dy+1) + (dx+1)
                 c = col;
             } else {
-                const int tg = col >> 3, pr = 4 * (set % 3) + tg;
+                const int tg = col >> 3, pr = 4 * (wv % 3) + tg;
                 if (pr >= 9) continue;
-                t = 9 * (pr / 3) + 3 * (pr % 3) + set / 3;
+                t = 9 * (pr / 3) + 3 * (pr % 3) + wv / 3;
                 c = col & 7;
             }
             wb[(t * 32 + o) * 32 + c] = acc[si][r];
@@ -444,7 +437,7 @@ __global__ __launch_bounds__(CONV_THR) void k_wgrad(const uint16_t* __restrict__
     if (tid < COUT) {  // output channel o = tid: threads with og = 8 (o / 8), in order
         const int g = tid >> 3, q = tid & 7;
         float sacc = 0.0f;
-        for (int j = g; j < (NVD < CONV_THR ? NVD : CONV_THR); j += COUT / 8) sacc += bsum[j * 8 + q];
+        for (int j = g; j < (NVD < WG_THR ? NVD : WG_THR); j += COUT / 8) sacc += bsum[j * 8 + q];
         wsb[blockIdx.x * 32 + tid] = sacc;
     }
 }
@@ -682,7 +675,7 @@ int status(hipError_t e) { return e == hipSuccess ? MHD_OK : MHD_ERR_DEVICE; }
 size_t wgrad_lds(int cin, int n)
 {
     return 2 * (cin * 3 * ((CONV_CELLS / n + 2) * n + 8) + 3 * 32 * (CONV_CELLS + 8)) +
-           4 * CONV_THR * 8;
+           4 * WG_THR * 8;
 }
 
 // Slabs of CONV_CELLS cells per plane and z chunks of zc planes, so that
@@ -742,7 +735,7 @@ hipError_t launch_wgrad(const uint16_t* x, const uint16_t* dz, int n, int batch,
     conv_chunks(n, batch, columns, nch, zc);
     const int blocks = columns * nch;
     float* wsb = ws + (size_t)blocks * 27 * 32 * 32;
-    hipLaunchKernelGGL((k_wgrad<CIN, COUT>), dim3(blocks), dim3(CONV_THR), wgrad_lds(CIN, n), st,
+    hipLaunchKernelGGL((k_wgrad<CIN, COUT>), dim3(blocks), dim3(WG_THR), wgrad_lds(CIN, n), st,
                        x, dz, n, ilog2(n), nch, zc, ws, wsb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -16,8 +16,9 @@
 //     lane's registers, so waves 0-3 take input channels 0-15 and waves 4-7
 //     channels 16-31, each over 64 cells (two M tiles); wave w and w+4 then
 //     add their partial sums through LDS, each finishing one tile.
-//   * weight gradient: M = output channels, N = input channels (or 4 taps x
-//     8 channels for 8-channel inputs), K = cells.  Over one full periodic
+//   * weight gradient (9 waves): M = output channels, N = input channels (or
+//     4 taps x 8 channels for 8-channel inputs), K = cells; wave w owns the
+//     taps of x shift w/3 - 1 and z offset w%3 - 1.  Over one full periodic
 //     x-row, sum_x dz(x) x(x + dx) = sum_q dz(q - dx) x(q), so the x shift is
 //     moved onto three pre-shifted LDS copies of the dz plane and every
 //     fragment is 8 consecutive, 16-byte aligned cells of one channel.
@@ -65,19 +66,21 @@ constexpr int NTHR = 256;
 // 2: data gradient (times GELU'(zprev), BF16).
 //
 // A block of CONV_THR threads owns a slab of CONV_CELLS / n full periodic
-// rows (CONV_CELLS cells per plane, 32 per wave) and marches it through a
-// chunk of zc planes.  LDS holds the weights and a ring of three planes of
-// the slab plus one periodic row on each side (channels last); plane p+2 is
-// fetched into registers while plane p is computed, so each input value is
-// read from memory (1 + 2 RY^-1)(1 + 2 zc^-1) times instead of once per
-// 3 x (rows + 2) neighbourhood of a small tile.
+// rows (CONV_CELLS cells per plane: 32 per wave for 8 input channels, 64 per
+// wave and half of K for 32) and marches it through a chunk of zc planes.
+// LDS holds a ring of three planes of the slab plus one periodic row on each
+// side (channels last) and, for 32 input channels, the partial-sum hand-over
+// area; the weights stay in registers.  Plane p+2 is fetched into registers
+// while plane p is computed, so each input value is read from memory
+// (1 + 2 RY^-1)(1 + 2 zc^-1) times instead of once per 3 x (rows + 2)
+// neighbourhood of a small tile.
 constexpr int CONV_THR = 512;
 constexpr int WG_THR = 576;  // weight gradient: 9 waves, one per (dx, dz) tap triple
-constexpr int CONV_CELLS = 256;  // cells per plane per block: 8 waves x 32
+constexpr int CONV_CELLS = 256;  // cells per plane per block
 
-// LDS row pitches (elements), padded so that consecutive lanes' 16-byte
-// fragment reads start an odd number of 16-byte units apart (no bank
-// conflicts): per cell of the input ring, per output channel of the weights.
+// LDS row pitch (elements) per cell of the input ring, padded so that
+// consecutive lanes' 16-byte fragment reads start an odd number of 16-byte
+// units apart (no bank conflicts).
 template <int CIN>
 constexpr int conv_cp() { return CIN == 32 ? CIN + 8 : CIN; }
 

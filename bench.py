@@ -218,12 +218,48 @@ def cpu_baseline(inputs, wl, n1=256):
                        f"same 8-field Fourier-mode recipe, {dt:.1f} s")
 
 
+def oracle_sweep(inputs, wl, sizes=(64, 256)):
+    """The oracle (one RK3 step, same recipe) at each size with one OpenMP
+    thread and with every host thread, plus the host's CPU model: the CPU
+    side of the measurement, beside the GPU numbers.  Runs on the host only."""
+    import ctypes
+    import oracle
+    gomp = ctypes.CDLL("libgomp.so.1")
+    everyone = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    model = "unknown"
+    if os.path.exists("/proc/cpuinfo"):
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    runs = []
+    for n1 in sizes:
+        n = (n1, n1, n1)
+        f = inputs.fourier_modes(n, wl["kmax"], wl["amp"], wl["seed"])
+        p = oracle.Params(*n)
+        for threads in sorted({1, everyone}):
+            gomp.omp_set_num_threads(threads)
+            t = time.perf_counter()
+            oracle.step(f, wl["dt"], p, 1)
+            dt = time.perf_counter() - t
+            runs.append(dict(n=n1, threads=threads, seconds=round(dt, 3),
+                             gcups=round(3 * n1 ** 3 / dt / 1e9, 6)))
+            print(f"# oracle {n1}^3, {threads} thread(s): {dt:.2f} s", file=sys.stderr, flush=True)
+    gomp.omp_set_num_threads(everyone)
+    return dict(cpu=model, threads_available=everyone, runs=runs)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--oracle-sweep", action="store_true",
+                    help="only time the CPU oracle (one thread and every thread, at the "
+                         "--oracle-sizes grids) and print one JSON line; needs no GPU")
+    ap.add_argument("--oracle-sizes", default="64,256",
+                    help="comma list of grid sizes n (n^3) for --oracle-sweep")
     ap.add_argument("--precisions", default=None,
                     help="comma list of f64, f32c, f32 (default: f64,f32c; f32c for "
                          "the large workload)")
@@ -244,6 +280,16 @@ def main():
         print("bench.py: this path is one GPU's share of the domain and has no multi-GPU "
               "mode; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.oracle_sweep:
+        from paper_2103_01597_amd import inputs
+        wl = inputs.WORKLOADS[args.workload]
+        sizes = tuple(int(v) for v in args.oracle_sizes.split(","))
+        print(json.dumps({"oracle_sweep": oracle_sweep(inputs, wl, sizes),
+                          "recipe": f"the {args.workload} field recipe (8 fields, {wl['amp']:g} x "
+                                    f"Fourier modes |k|<={wl['kmax']}, seed {wl['seed']}, "
+                                    f"dt {wl['dt']:g}) at "
+                                    + ", ".join(f"{v}^3" for v in sizes)}))
+        return
 
     import torch
     from paper_2103_01597_amd import inputs, mhd

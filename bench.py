@@ -172,13 +172,16 @@ def run_precision(mhd, inputs, torch, name, prec, steps, warmup, kernel, segment
 
 def kernel_source_hash(kernel):
     """SHA-256 of the sources a fused kernel is built from (its own file and
-    the headers it shares)."""
+    the headers it shares) and of its compile flags."""
     import hashlib
+    from paper_2103_01597_amd import build as hip_build
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2103_01597_amd", "csrc")
     for name in (KERNEL_SOURCE[kernel], "rk3_common.hpp", "mhd_internal.hpp"):
         with open(os.path.join(csrc, name), "rb") as fh:
             h.update(fh.read())
+    flags = hip_build.FLAGS + hip_build.PER_FILE.get(KERNEL_SOURCE[kernel], [])
+    h.update(" ".join(f for f in flags if not f.startswith("/")).encode())
     return h.hexdigest()
 
 

@@ -2,7 +2,11 @@
 
 Every kernel is compiled for gfx950 only.  Packed-FP32 instruction
 selection is disabled (-packed-fp32-ops), FP contraction is left at the
-compiler default for device code.
+compiler default for device code.  The two fused stencil kernels are
+scheduled with the backend's iterative ILP strategy: they are bound by
+instruction latency, and it measured 3-5% faster at 512^3 than the default
+scheduler (the strategy only reorders instructions; the results do not
+change).
 """
 import glob
 import os
@@ -20,6 +24,13 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Wall", "-Wno-unused-result", "-I", os.path.join(ROOT, "include")]
 
 
+# extra flags per source file
+PER_FILE = {
+    "rk3_split.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
+    "rk3_tiled.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
+}
+
+
 def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
@@ -28,7 +39,8 @@ def build(verbose: bool = False, extra=()) -> str:
     objs = []
     for src in sources():
         obj = os.path.join(CSRC, os.path.basename(src)[:-4] + ".o")
-        cmd = [HIPCC, *[f for f in FLAGS if f != "-shared"], *extra, "-c", src, "-o", obj]
+        own = PER_FILE.get(os.path.basename(src), [])
+        cmd = [HIPCC, *[f for f in FLAGS if f != "-shared"], *own, *extra, "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)

@@ -34,6 +34,15 @@
 #include "rk3_common.hpp"
 
 namespace mhd {
+
+// FP64 at radius 4 is instantiated in a second translation unit,
+// rk3_split_dflt.hip (this file with MHD_DEFAULT_SCHED defined), which the
+// build compiles with the default instruction scheduler: the iterative ILP
+// scheduler this file is built with makes it slower (measured at 512^3).
+hipError_t launch_rk3_split_dflt(const Grid& g, const Phys& P, const Phys* P_dev, const Box& bx,
+                                 int s, const void* f_in, void* f_out, void* w, double dt,
+                                 hipStream_t st);
+
 namespace {
 
 #ifndef MHD_SPLIT_TX
@@ -618,7 +627,10 @@ hipError_t launch_order(const Grid& g, const Phys& P, const Phys* P_dev, int pre
     switch (precision) {
     case MHD_F64:
         static_assert(lds_bytes<MHD_F64, RAD>() <= 160 * 1024, "FP64 ring exceeds the LDS");
-        return launch_one<MHD_F64, RAD>(g, P, P_dev, bx, s, f_in, f_out, w, nullptr, dt, st);
+        if constexpr (RAD == 4)
+            return launch_rk3_split_dflt(g, P, P_dev, bx, s, f_in, f_out, w, dt, st);
+        else
+            return launch_one<MHD_F64, RAD>(g, P, P_dev, bx, s, f_in, f_out, w, nullptr, dt, st);
     case MHD_F32C:
         return launch_one<MHD_F32C, RAD>(g, P, P_dev, bx, s, f_in, f_out, w, comp, dt, st);
     default: return launch_one<MHD_F32, RAD>(g, P, P_dev, bx, s, f_in, f_out, w, nullptr, dt, st);
@@ -627,6 +639,7 @@ hipError_t launch_order(const Grid& g, const Phys& P, const Phys* P_dev, int pre
 
 }  // namespace
 
+#ifndef MHD_DEFAULT_SCHED
 // P (host copy) sets the stencil scales; P_dev (device copy of the same
 // values) is what the kernel's physics reads.  The stencil radius is the
 // grid's halo width g.r (1..4).
@@ -642,5 +655,13 @@ hipError_t launch_rk3_split(const Grid& g, const Phys& P, const Phys* P_dev, int
     default: return hipErrorInvalidValue;
     }
 }
+#else
+hipError_t launch_rk3_split_dflt(const Grid& g, const Phys& P, const Phys* P_dev, const Box& bx,
+                                 int s, const void* f_in, void* f_out, void* w, double dt,
+                                 hipStream_t st)
+{
+    return launch_one<MHD_F64, 4>(g, P, P_dev, bx, s, f_in, f_out, w, nullptr, dt, st);
+}
+#endif
 
 }  // namespace mhd

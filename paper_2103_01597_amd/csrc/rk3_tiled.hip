@@ -573,18 +573,39 @@ hipError_t launch_order(const Grid& g, const Phys& P, int precision, const Box& 
 
 }  // namespace
 
+// Radii 1 and 4 are instantiated in a second translation unit,
+// rk3_tiled_dflt.hip (this file with MHD_DEFAULT_SCHED defined), which the
+// build compiles with the default instruction scheduler: the iterative ILP
+// scheduler this file is built with makes them slower (measured at 512^3).
+hipError_t launch_rk3_tiled_dflt(const Grid& g, const Phys& P, int precision, const Box& bx, int s,
+                                 const void* f_in, void* f_out, void* w, void* comp, double dt,
+                                 hipStream_t st);
+
+#ifndef MHD_DEFAULT_SCHED
 // The stencil radius is the grid's halo width g.r (1..4).
 hipError_t launch_rk3_tiled(const Grid& g, const Phys& P, int precision, const Box& bx, int s,
                             const void* f_in, void* f_out, void* w, void* comp, double dt,
                             hipStream_t st)
 {
     switch (g.r) {
-    case 1: return launch_order<1>(g, P, precision, bx, s, f_in, f_out, w, comp, dt, st);
+    case 1:
+    case 4: return launch_rk3_tiled_dflt(g, P, precision, bx, s, f_in, f_out, w, comp, dt, st);
     case 2: return launch_order<2>(g, P, precision, bx, s, f_in, f_out, w, comp, dt, st);
     case 3: return launch_order<3>(g, P, precision, bx, s, f_in, f_out, w, comp, dt, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+#else
+hipError_t launch_rk3_tiled_dflt(const Grid& g, const Phys& P, int precision, const Box& bx, int s,
+                                 const void* f_in, void* f_out, void* w, void* comp, double dt,
+                                 hipStream_t st)
+{
+    switch (g.r) {
+    case 1: return launch_order<1>(g, P, precision, bx, s, f_in, f_out, w, comp, dt, st);
     case 4: return launch_order<4>(g, P, precision, bx, s, f_in, f_out, w, comp, dt, st);
     default: return hipErrorInvalidValue;
     }
 }
+#endif
 
 }  // namespace mhd

@@ -147,7 +147,7 @@ def test_conv_dgrad(nn, cin_dz, cprev, n, batch):
 
 
 @pytest.mark.parametrize("cin,cout", [(8, 32), (32, 32), (32, 8)])
-@pytest.mark.parametrize("n,batch", [(16, 2), (32, 1)])
+@pytest.mark.parametrize("n,batch", [(16, 2), (32, 1), (64, 1)])
 def test_conv_wgrad(nn, cin, cout, n, batch):
     import torch
     rng = np.random.default_rng(30 + cin + cout + n)

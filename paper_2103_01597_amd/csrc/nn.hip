@@ -445,40 +445,59 @@ __global__ __launch_bounds__(WG_THR) void k_wgrad(const uint16_t* __restrict__ x
     }
 }
 
+// Outputs per workgroup of k_wgrad_reduce: NTHR threads = RED_SEGS waves of
+// RED_OUT lanes, wave k summing the k-th quarter of the blocks' partials.
+constexpr int RED_SEGS = 4, RED_OUT = NTHR / RED_SEGS;
+
 __global__ __launch_bounds__(NTHR) void k_wgrad_reduce(const float* __restrict__ ws,
                                                        const float* __restrict__ wsb, int nblocks,
                                                        int cin, int cout, float* __restrict__ dw,
                                                        float* __restrict__ dbias)
 {
-    // one thread per weight (then per bias); the partials of consecutive
-    // blocks are fetched 8 at a time and added in block order
-    const int i = blockIdx.x * NTHR + threadIdx.x;
+    // One lane per weight (then per bias) in each of the RED_SEGS waves;
+    // wave k adds the partials of blocks [k q, (k+1) q) in block order,
+    // fetched 8 at a time, and the RED_SEGS segment sums are then added in
+    // segment order (deterministic)
+    __shared__ float part[RED_SEGS][RED_OUT];
+    const int lane = threadIdx.x % RED_OUT, seg = threadIdx.x / RED_OUT;
+    const int i = blockIdx.x * RED_OUT + lane;
     const int nw = cout * 27 * cin;
-    if (i >= nw + cout) return;
-    const float* src;
-    size_t stride;
-    if (i < nw) {
-        const int o = i / (27 * cin), rem = i - o * 27 * cin, t = rem / cin, c = rem - t * cin;
-        src = ws + (size_t)(t * 32 + o) * 32 + c;
-        stride = 27 * 32 * 32;
-    } else {
-        src = wsb + (i - nw);
-        stride = 32;
-    }
+    const bool valid = i < nw + cout;
     float s = 0.0f;
-    int bk = 0;
-    for (; bk + 8 <= nblocks; bk += 8) {
-        float v[8];
+    if (valid) {
+        const float* src;
+        size_t stride;
+        if (i < nw) {
+            const int o = i / (27 * cin), rem = i - o * 27 * cin, t = rem / cin, c = rem - t * cin;
+            src = ws + (size_t)(t * 32 + o) * 32 + c;
+            stride = 27 * 32 * 32;
+        } else {
+            src = wsb + (i - nw);
+            stride = 32;
+        }
+        const int q = (nblocks + RED_SEGS - 1) / RED_SEGS;
+        const int b0 = seg * q, b1 = min(b0 + q, nblocks);
+        int bk = b0;
+        for (; bk + 8 <= b1; bk += 8) {
+            float v[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = src[(size_t)(bk + j) * stride];
+            for (int j = 0; j < 8; ++j) v[j] = src[(size_t)(bk + j) * stride];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) s += v[j];
+            for (int j = 0; j < 8; ++j) s += v[j];
+        }
+        for (; bk < b1; ++bk) s += src[(size_t)bk * stride];
     }
-    for (; bk < nblocks; ++bk) s += src[(size_t)bk * stride];
-    if (i < nw)
-        dw[i] = s;
-    else
-        dbias[i - nw] = s;
+    part[seg][lane] = s;
+    __syncthreads();
+    if (seg == 0 && valid) {
+        float t = part[0][lane];
+#pragma unroll
+        for (int k = 1; k < RED_SEGS; ++k) t += part[k][lane];
+        if (i < nw)
+            dw[i] = t;
+        else
+            dbias[i - nw] = t;
+    }
 }
 
 // ------------------------------------------------------------ elementwise
@@ -743,8 +762,8 @@ hipError_t launch_wgrad(const uint16_t* x, const uint16_t* dz, int n, int batch,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int total = COUT * 27 * CIN + COUT;
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3((total + NTHR - 1) / NTHR), dim3(NTHR), 0, st, ws, wsb,
-                       blocks, CIN, COUT, dw, db);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((total + RED_OUT - 1) / RED_OUT), dim3(NTHR), 0, st, ws,
+                       wsb, blocks, CIN, COUT, dw, db);
     return hipGetLastError();
 }
 

@@ -2,11 +2,13 @@
 
 Every kernel is compiled for gfx950 only.  Packed-FP32 instruction
 selection is disabled (-packed-fp32-ops), FP contraction is left at the
-compiler default for device code.  The two fused stencil kernels are
-scheduled with the backend's iterative ILP strategy: they are bound by
-instruction latency, and it measured 3-5% faster at 512^3 than the default
-scheduler (the strategy only reorders instructions; the results do not
-change).
+compiler default for device code.  The two LDS stencil kernels
+(rk3_split.hip, rk3_tiled.hip) are scheduled with the backend's iterative
+ILP strategy: they are bound by instruction latency, and it measured up to
+4-7% faster at 512^3 than the default scheduler (the strategy only reorders
+instructions; the results do not change).  The instantiations it slows are
+compiled from rk3_split_dflt.hip and rk3_tiled_dflt.hip, which include the
+kernel files with MHD_DEFAULT_SCHED, with the default scheduler.
 """
 import glob
 import os

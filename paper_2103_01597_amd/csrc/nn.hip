@@ -184,6 +184,19 @@ __global__ __launch_bounds__(CONV_THR) void k_conv(const uint16_t* __restrict__ 
         __syncthreads();
         if (p + 1 < nz) load(z0 + p + 2);
         const int sb[3] = {(p % 3) * (RY + 2), ((p + 1) % 3) * (RY + 2), ((p + 2) % 3) * (RY + 2)};
+        const size_t c0 = (size_t)b * n3 + ((size_t)(z0 + p) << (2 * logn)) + ((size_t)y0 << logn);
+        // data gradient: the layer's pre-activations for this plane's outputs,
+        // fetched now so that their latency overlaps the MFMA loop
+        uint16_t zp[16];
+        if constexpr (MODE == 2) {
+            if (col < cout) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int cl = mbase + 32 * fin + 8 * (r >> 2) + 4 * h + (r & 3);
+                    zp[r] = zprev[(c0 + cl) * cout + col];
+                }
+            }
+        }
 
         floatx16 acc[NT];
 #pragma unroll
@@ -235,7 +248,6 @@ __global__ __launch_bounds__(CONV_THR) void k_conv(const uint16_t* __restrict__ 
 
         if (col < cout) {
             const float bv = (MODE == 2) ? 0.0f : bias[col];
-            const size_t c0 = (size_t)b * n3 + ((size_t)(z0 + p) << (2 * logn)) + ((size_t)y0 << logn);
             const floatx16& res = acc[0];
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
@@ -248,7 +260,7 @@ __global__ __launch_bounds__(CONV_THR) void k_conv(const uint16_t* __restrict__ 
                 } else if constexpr (MODE == 1) {
                     outf[o] = v;
                 } else {
-                    out0[o] = f2bf(v * gelu_grad(bf2f(zprev[o])));
+                    out0[o] = f2bf(v * gelu_grad(bf2f(zp[r])));
                 }
             }
         }

@@ -47,11 +47,37 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint
 // conversion instruction on gfx950.
 __device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
-__device__ __forceinline__ float gelu(float v) { return 0.5f * v * (1.0f + erff(v * 0.70710678118654752f)); }
+// erfc(z) / 2 for z >= 0 as t exp(-z^2 + P(t)) / 2 with t = 1 / (1 + z/2)
+// and P the degree-9 Chebyshev fit of Press et al. (Numerical Recipes,
+// Sec. 6.2): relative error below 1.2e-7 in exact arithmetic, and branch
+// free.  In FP32 the GELU built on it stays within 2e-5 relative error on
+// [-12, 12], the negative tail included (where 1 + erf(x) would cancel).
+__device__ __forceinline__ float half_erfc(float z)
+{
+    const float t = __builtin_amdgcn_rcpf(1.0f + 0.5f * z);
+    float p = 0.17087277f;
+    p = fmaf(p, t, -0.82215223f);
+    p = fmaf(p, t, 1.48851587f);
+    p = fmaf(p, t, -1.13520398f);
+    p = fmaf(p, t, 0.27886807f);
+    p = fmaf(p, t, -0.18628806f);
+    p = fmaf(p, t, 0.09678418f);
+    p = fmaf(p, t, 0.37409196f);
+    p = fmaf(p, t, 1.00002368f);
+    p = fmaf(p, t, -1.26551223f);
+    return 0.5f * t * __expf(fmaf(-z, z, p));
+}
+// Standard normal distribution function Phi(v) = erfc(-v / sqrt 2) / 2.
+__device__ __forceinline__ float normal_cdf(float v)
+{
+    const float h = half_erfc(fabsf(v) * 0.70710678118654752f);
+    return v >= 0.0f ? 1.0f - h : h;
+}
+// GELU(v) = v Phi(v) (exact-erf form) and its derivative Phi(v) + v phi(v).
+__device__ __forceinline__ float gelu(float v) { return v * normal_cdf(v); }
 __device__ __forceinline__ float gelu_grad(float v)
 {
-    return 0.5f * (1.0f + erff(v * 0.70710678118654752f)) +
-           v * __expf(-0.5f * v * v) * 0.39894228040143268f;
+    return normal_cdf(v) + v * __expf(-0.5f * v * v) * 0.39894228040143268f;
 }
 
 __device__ __forceinline__ bf16x8 frag(const uint16_t* p)  // 16-byte aligned

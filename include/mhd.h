@@ -156,8 +156,9 @@ const char *mhd_strerror(int status);
 
 /* Periodic halo fill of all 8 fields in place (Section 3.3): every halo
  * cell (x, y, z) of the padded grid receives the interior cell obtained by
- * mapping each coordinate s with ((s - 3) mod n) + 3; edges and corners
- * included.  Errors: MHD_ERR_INVALID (NULL). */
+ * mapping each coordinate s with ((s - r) mod n) + r, r = order/2 the halo
+ * width (mhd_layout.halo); edges and corners included.
+ * Errors: MHD_ERR_INVALID (NULL). */
 int mhd_halo_periodic(mhd_ctx *ctx, void *fields, void *stream);
 
 /* One RK3 substep s in {0, 1, 2} (Section 4; Appendix B):

@@ -1,8 +1,8 @@
 // Fused RHS + RK3 substep, direct form: one thread per interior cell, every
 // stencil point read from global memory (the L1/L2 caches catch the reuse),
 // for every stencil order 2r, r = 1..4.
-// It is the plain baseline next to the LDS-tiled z-marching kernel and the
-// path used for grids too small for that kernel's tiles.
+// It is the plain baseline next to the LDS-tiled z-marching kernels, run
+// only when a caller asks for it (MHD_KERNEL_DIRECT); AUTO never picks it.
 //
 // Per cell it evaluates the derivatives of Section 4, Eq. (stencil-fd) --
 // first and pure second derivatives on the axis lines, mixed derivatives on

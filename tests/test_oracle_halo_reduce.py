@@ -58,3 +58,28 @@ def test_ulps_definition(oracle_mod):
     eps = np.array([2.0 ** -52, 2.0 ** -52, 2.0 ** -51, 2.0 ** -53])
     c = m + 2 * eps
     assert np.allclose(oracle_mod.ulps(c, m), 2.0)
+
+
+def test_rel_err_hand_computed(oracle_mod):
+    """The parity metric is the infinity-norm relative error max|c - m| /
+    max|m| of one field (model m = oracle, candidate c).  Values chosen so
+    that every plausible variant gives a different number: the pointwise
+    maximum of |c - m| / |m| (0.25), normalising by the candidate (1/7), the
+    mean or L2 norms (0.14, 0.145), a signed difference (0.09375), or max(m)
+    without the absolute value (1/3)."""
+    m = np.array([3.0, -8.0, 1.0, 0.5])
+    c = np.array([3.75, -7.0, 1.0, 0.5])
+    assert oracle_mod.rel_err(c, m) == 0.125
+    assert oracle_mod.rel_err(m, c) == 1.0 / 7.0  # the arguments are not symmetric
+    # shape does not matter: the norms run over every element of the field
+    assert oracle_mod.rel_err(c.reshape(2, 2), m.reshape(2, 2)) == 0.125
+    # identical fields, and an all-zero model (the absolute error is returned)
+    assert oracle_mod.rel_err(m, m) == 0.0
+    assert oracle_mod.rel_err(np.array([0.0, -2e-3]), np.zeros(2)) == 2e-3
+    # one NaN or Inf anywhere in the candidate makes the error non-finite, so
+    # no bar of the form err <= tol can pass
+    for bad in (np.nan, np.inf):
+        cc = c.copy()
+        cc[2] = bad
+        e = oracle_mod.rel_err(cc, m)
+        assert not (e <= 1.0)

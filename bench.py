@@ -72,6 +72,37 @@ def time_segmented(S, torch, bufs, cur, w, comp, dt, steps, cells):
                 gcups=round(3 * cells * steps / (ms * 1e-3) / 1e9, 4))
 
 
+def achievable_bandwidth(mhd, torch, nbytes=2 << 30, launches=10):
+    """Achievable HBM bandwidth: the library's plain copy and triad kernels
+    (with and without non-temporal hints) over arrays of nbytes each, far
+    larger than the last-level cache; GB/s = bytes read and written per
+    launch / average launch time (HIP events on the launch stream)."""
+    stream = torch.cuda.current_stream()
+    a = torch.full((nbytes // 8,), 1.0, dtype=torch.float64, device="cuda")
+    b = torch.full_like(a, 2.0)
+    c = torch.empty_like(a)
+    moved = {"copy": 2 * nbytes, "copy_nt": 2 * nbytes, "triad": 3 * nbytes, "triad_nt": 3 * nbytes}
+    out = {}
+    for kind in ("copy", "copy_nt", "triad", "triad_nt"):
+        for _ in range(2):
+            mhd.bandwidth_probe(kind, a, b, c)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(launches)]
+        for e0, e1 in ev:
+            e0.record(stream)
+            mhd.bandwidth_probe(kind, a, b, c)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        ms = sum(e0.elapsed_time(e1) for e0, e1 in ev) / launches
+        out[kind] = round(moved[kind] / (ms * 1e-3) / 1e9, 1)
+    ok = bool(torch.all(c == 7.0).item())  # the last launch was a triad: 1 + 3 * 2
+    del a, b, c
+    torch.cuda.empty_cache()
+    best = max(out, key=out.get)
+    return dict(gbs=out, best_kind=best, best_gbs=out[best], array_bytes=nbytes,
+                launches=launches, result_ok=ok)
+
+
 def order_study(mhd, inputs, torch, steps=5, warmup=1, name="sub256"):
     """Time per cell per RK3 step for the stencil orders 2, 4, 6 and 8 at
     256^3 (the single-GPU part of the paper's order study, Section 5), FP64
@@ -114,7 +145,8 @@ def order_study(mhd, inputs, torch, steps=5, warmup=1, name="sub256"):
     return out
 
 
-def run_precision(mhd, inputs, torch, name, prec, steps, warmup, kernel, segmented=False):
+def run_precision(mhd, inputs, torch, name, prec, steps, warmup, kernel, segmented=False,
+                  repeats=5):
     wl = inputs.WORKLOADS[name]
     n = wl["shape"]
     cells = n[0] * n[1] * n[2]
@@ -150,6 +182,17 @@ def run_precision(mhd, inputs, torch, name, prec, steps, warmup, kernel, segment
     sum_kern_ms = sum(sum(r) for r in kern_ms)
     alg_bytes = steps * cells * sum(BYTES_PER_CELL[prec])
     achieved = alg_bytes / (sum_kern_ms * 1e-3) / 1e9
+    # repeats of the same K steps (mhd_step, the same launch sequence) for
+    # the spread; the first region above is the reported one
+    reps = [total_ms / steps]
+    for _ in range(repeats - 1):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        cur = S.step(bufs, cur, w, comp, dt, steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        reps.append(e0.elapsed_time(e1) / steps)
     nonfinite = S.reduce(bufs[cur], 0, "nonfinite")
     seg = time_segmented(S, torch, bufs, cur, w, comp, dt, steps, cells) if segmented else None
     res = dict(
@@ -163,6 +206,8 @@ def run_precision(mhd, inputs, torch, name, prec, steps, warmup, kernel, segment
         nonfinite=nonfinite,
         kernel=kernel,
         segmented=seg,
+        ms_per_step_repeats=[round(v, 4) for v in reps],
+        median_gcups=3 * cells / (float(np.median(reps)) * 1e-3) / 1e9,
     )
     S.close()
     del bufs, w, comp
@@ -276,6 +321,11 @@ def main():
     ap.add_argument("--kernel", default=None, choices=["split", "tiled", "direct"],
                     help="fused-substep kernel (default: the library's default for each "
                          "precision: split for f64, tiled otherwise)")
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="timed regions of --steps steps per precision (the first is "
+                         "the reported one; the median is reported beside it)")
+    ap.add_argument("--no-bandwidth", action="store_true",
+                    help="skip the copy/triad measurement of achievable HBM bandwidth")
     args = ap.parse_args()
     if args.precisions is None:
         args.precisions = "f32c" if args.workload == "large1024x512x512" else "f64,f32c"
@@ -299,10 +349,15 @@ def main():
     mhd.lib()
     torch.cuda.set_device(0)
     wl = inputs.WORKLOADS[args.workload]
+    bw = None
+    if not args.no_bandwidth:
+        bw = achievable_bandwidth(mhd, torch)
+        print(f"# bandwidth: {json.dumps(bw)}", file=sys.stderr, flush=True)
     results = {}
     for prec in args.precisions.split(","):
         results[prec] = run_precision(mhd, inputs, torch, args.workload, prec, args.steps,
-                                      args.warmup, args.kernel, not args.no_segmented)
+                                      args.warmup, args.kernel, not args.no_segmented,
+                                      max(1, args.repeats))
         print(f"# {prec}: {json.dumps(results[prec])}", file=sys.stderr, flush=True)
 
     main_prec = "f64" if "f64" in results else next(iter(results))
@@ -330,7 +385,13 @@ def main():
                      "traffic": measured_traffic(r["kernel"], main_prec, args.workload),
                      "kernel": KERNEL_SYMBOL[r["kernel"]],
                      "kernel_ms_avg": round(r["kernel_ms_avg"], 4)},
+        "ms_per_step_repeats": r["ms_per_step_repeats"],
+        "median_gcups": round(r["median_gcups"], 4),
     }
+    if bw is not None:
+        line["roofline"]["achievable"] = bw["best_gbs"]
+        line["roofline"]["frac_of_achievable"] = round(r["kernel_gbs"] / bw["best_gbs"], 4)
+        line["bandwidth"] = bw
     for prec, rr in results.items():
         if prec != main_prec:
             line[f"{prec}_gcups"] = round(rr["gcups"], 4)
@@ -338,6 +399,9 @@ def main():
             line[f"{prec}_kernel_ms_avg"] = round(rr["kernel_ms_avg"], 4)
             line[f"{prec}_kernel"] = KERNEL_SYMBOL[rr["kernel"]]
             line[f"{prec}_traffic"] = measured_traffic(rr["kernel"], prec, args.workload)
+            line[f"{prec}_median_gcups"] = round(rr["median_gcups"], 4)
+            if bw is not None:
+                line[f"{prec}_frac_of_achievable"] = round(rr["kernel_gbs"] / bw["best_gbs"], 4)
     segs = {prec: rr["segmented"] for prec, rr in results.items() if rr["segmented"]}
     if segs:
         line["segmented"] = segs

@@ -248,6 +248,22 @@ int mhd_step_segmented(mhd_ctx *ctx, void *const f[2], int32_t *cur, void *w, vo
 int mhd_reduce(mhd_ctx *ctx, const void *fields, int32_t field, int32_t op,
                double *out_host, void *stream);
 
+/* ------------------------------------------------------- measurement
+ * Achievable HBM bandwidth, the practical ceiling beside the 8 TB/s peak
+ * (Section 5 confirms bandwidth figures by measurement).  One launch of a
+ * plain streaming kernel over arrays of `bytes` bytes (a multiple of 16):
+ *   MHD_BW_COPY     c = a               (bytes read, bytes written)
+ *   MHD_BW_TRIAD    c = a + 3 * b, FP64 (2 * bytes read, bytes written)
+ * and the same with non-temporal loads and stores (_NT).  a, b, c: device
+ * buffers owned by the caller, b unused by the copies; c must not alias a
+ * or b.  Asynchronous on `stream`.  Errors: MHD_ERR_INVALID (unknown kind,
+ * NULL, aliasing, size), MHD_ERR_DEVICE (launch failure). */
+enum mhd_bandwidth_kind {
+    MHD_BW_COPY = 0, MHD_BW_COPY_NT = 1, MHD_BW_TRIAD = 2, MHD_BW_TRIAD_NT = 3
+};
+int mhd_bandwidth_probe(int32_t kind, const void *a, const void *b, void *c, int64_t bytes,
+                        void *stream);
+
 #ifdef __cplusplus
 }
 #endif

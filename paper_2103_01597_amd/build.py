@@ -38,15 +38,23 @@ def sources():
 
 
 def build(verbose: bool = False, extra=()) -> str:
-    objs = []
+    from concurrent.futures import ThreadPoolExecutor
+    cmds, objs = [], []
     for src in sources():
         obj = os.path.join(CSRC, os.path.basename(src)[:-4] + ".o")
         own = PER_FILE.get(os.path.basename(src), [])
-        cmd = [HIPCC, *[f for f in FLAGS if f != "-shared"], *own, *extra, "-c", src, "-o", obj]
+        cmds.append([HIPCC, *[f for f in FLAGS if f != "-shared"], *own, *extra, "-c", src,
+                     "-o", obj])
+        objs.append(obj)
+
+    def compile_one(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
-        objs.append(obj)
+
+    # one hipcc per translation unit, a few at a time
+    with ThreadPoolExecutor(max_workers=max(1, min(8, os.cpu_count() or 1))) as pool:
+        list(pool.map(compile_one, cmds))
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -28,7 +28,8 @@ STATUS = {0: "MHD_OK", 1: "MHD_ERR_INVALID", 2: "MHD_ERR_NO_DEVICE", 3: "MHD_ERR
 EXPORTS = ("mhd_config_default", "mhd_init", "mhd_finalize", "mhd_strerror",
            "mhd_halo_periodic", "mhd_rk3_substep", "mhd_step", "mhd_halo_segment_elems",
            "mhd_halo_pack", "mhd_halo_unpack", "mhd_halo_exchange_self", "mhd_rk3_substep_box",
-           "mhd_step_segmented", "mhd_reduce")
+           "mhd_step_segmented", "mhd_reduce", "mhd_bandwidth_probe")
+BW_KINDS = {"copy": 0, "copy_nt": 1, "triad": 2, "triad_nt": 3}
 
 
 class Config(ctypes.Structure):
@@ -90,9 +91,10 @@ def lib():
     L.mhd_rk3_substep_box.argtypes = [vp, i32, ctypes.POINTER(Box), vp, vp, vp, vp, dbl, vp]
     L.mhd_step_segmented.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(i32), vp, vp, dbl,
                                      i32, vp, vp, vp, vp]
+    L.mhd_bandwidth_probe.argtypes = [i32, vp, vp, vp, ctypes.c_int64, vp]
     for fn in ("mhd_init", "mhd_halo_periodic", "mhd_rk3_substep", "mhd_step", "mhd_reduce",
                "mhd_halo_pack", "mhd_halo_unpack", "mhd_halo_exchange_self",
-               "mhd_rk3_substep_box", "mhd_step_segmented"):
+               "mhd_rk3_substep_box", "mhd_step_segmented", "mhd_bandwidth_probe"):
         getattr(L, fn).restype = ctypes.c_int
     _lib = L
     return L
@@ -275,3 +277,11 @@ class Solver:
         _check("mhd_reduce", lib().mhd_reduce(self._ctx, _ptr(buf), q, RED_OPS[op],
                                               ctypes.byref(out), _stream(stream)))
         return out.value
+
+
+def bandwidth_probe(kind, a, b, c, stream=None):
+    """One launch of a streaming kernel (``BW_KINDS``) over the byte size
+    of ``c`` (flat device tensors; ``b`` is unused by the copies)."""
+    nbytes = c.numel() * c.element_size()
+    _check("mhd_bandwidth_probe", lib().mhd_bandwidth_probe(BW_KINDS[kind], _ptr(a), _ptr(b),
+                                                            _ptr(c), nbytes, _stream(stream)))

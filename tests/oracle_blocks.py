@@ -56,7 +56,7 @@ def block_reference(f0, cells, p: "oracle.Params", dt: float, nsub: int):
         iz = (k[c] - r + np.arange(mz)) % nz
         iy = (j[c] - r + np.arange(my)) % ny
         ix = (i[c] - r + np.arange(mx)) % nx
-        blk = np.ascontiguousarray(f0[:, iz][:, :, iy][:, :, :, ix], dtype=np.float64)
+        blk = np.ascontiguousarray(f0[np.ix_(np.arange(8), iz, iy, ix)], dtype=np.float64)
         w = np.zeros_like(blk)
         for t in range(nsub):
             blk, w = oracle.substep(t % 3, blk, w, dt, pb)
@@ -81,11 +81,15 @@ def sample_cells(n, ncells, seed):
 _CACHE = {}
 
 
-def workload_reference(wl_name, ncells=400, seed=0):
+def workload_reference(wl_name, ncells=400, seed=0, fp32_state=False):
     """(params, initial state, cells, fs, ws, per-field max |f0|) for one
-    RK3 step of a named workload, fs/ws from block_reference.  The most
-    recent workload is cached (the state of a large one is gigabytes)."""
-    key = (wl_name, ncells, seed)
+    RK3 step of a named workload, fs/ws from block_reference.  With
+    fp32_state the initial state is first rounded to FP32 (the state an
+    FP32-storage run starts from), so that a comparison measures the
+    arithmetic and storage of the run, not the rounding of its input.  The
+    most recent workload is cached (the state of a large one is
+    gigabytes)."""
+    key = (wl_name, ncells, seed, fp32_state)
     if key not in _CACHE:
         _CACHE.clear()
         wl = inputs.WORKLOADS[wl_name]
@@ -93,6 +97,8 @@ def workload_reference(wl_name, ncells=400, seed=0):
         lengths = wl.get("lengths", (2 * math.pi,) * 3)
         p = oracle.Params(*n, lx=lengths[0], ly=lengths[1], lz=lengths[2])
         f0 = inputs.workload_state(wl_name)
+        if fp32_state:
+            f0 = f0.astype(np.float32).astype(np.float64)
         cells = sample_cells(n, ncells, seed)
         fs, ws = block_reference(f0, cells, p, wl["dt"], 3)
         scale = np.abs(f0).reshape(8, -1).max(axis=1)

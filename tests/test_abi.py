@@ -108,6 +108,20 @@ def test_null_arguments(L):
     L.mhd_finalize(None)
 
 
+def test_bandwidth_probe_validation(L):
+    """Invalid probe arguments are rejected before anything is launched."""
+    vp = ctypes.c_void_p
+    assert L.mhd_bandwidth_probe(4, vp(16), vp(32), vp(48), 1 << 20, None) == 1
+    assert L.mhd_bandwidth_probe(-1, vp(16), vp(32), vp(48), 1 << 20, None) == 1
+    assert L.mhd_bandwidth_probe(0, None, None, vp(48), 1 << 20, None) == 1
+    assert L.mhd_bandwidth_probe(0, vp(16), None, None, 1 << 20, None) == 1
+    assert L.mhd_bandwidth_probe(0, vp(16), None, vp(48), 1000, None) == 1  # not 16-byte units
+    assert L.mhd_bandwidth_probe(1, vp(16), None, vp(48), 0, None) == 1
+    assert L.mhd_bandwidth_probe(2, vp(16), None, vp(48), 1 << 20, None) == 1  # triad needs b
+    assert L.mhd_bandwidth_probe(3, vp(16), vp(48), vp(48), 1 << 20, None) == 1  # b aliases c
+    assert L.mhd_bandwidth_probe(0, vp(48), None, vp(48), 1 << 20, None) == 1  # a aliases c
+
+
 @pytest.mark.parametrize("ok", [dict(), dict(order=2), dict(order=8, kernel=1),
                                 dict(order=8, kernel=0), dict(order=4, kernel=2),
                                 dict(order=2, kernel=2), dict(order=8, kernel=2, precision=1),

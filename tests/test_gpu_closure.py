@@ -378,9 +378,11 @@ def test_closure_gains_over_plain_coarse_run(nn):
     X, D, _ = closure.generate_pairs(runs=4, pairs_per_run=60, seed_base=100, log=say, **kw)
     trained, hist = closure.train(X, D, 16, epochs=10, batch=4, lr=2e-3, log=say)
     ep, ec, truth, plain, corr = closure.evaluate(trained, seed=1000, steps=40, **kw)
-    for i in (0, len(ep) - 1):
+    for i in sorted({0, 1, 4, 9, 19, len(ep) - 1}):
         say(f"step {i + 1} rel L2 plain    :", " ".join("%.3e" % e for e in ep[i]))
         say(f"step {i + 1} rel L2 corrected:", " ".join("%.3e" % e for e in ec[i]))
+    say("run mean plain    :", " ".join("%.3e" % e for e in ep.mean(axis=0)))
+    say("run mean corrected:", " ".join("%.3e" % e for e in ec.mean(axis=0)))
     assert hist[-1] < hist[0]
     assert np.all(np.isfinite(ec))
     assert np.mean(ec) < np.mean(ep)

@@ -3,11 +3,17 @@
 FP32C keeps the state in FP32 with a Kahan-compensated state update and
 evaluates every second-derivative sum in FP64; F32 (the ablation) does
 neither.  Bars (infinity-norm relative error per field, the oracle started
-from the same FP32-rounded state):
-  * after 1 step: <= 1e-6.  The state itself is stored to FP32 (half an
-    ulp, 6e-8 of its magnitude) and first derivatives of differences of
-    FP32 values carry relative errors of about 2^-24/(k h) ~ 1e-7.
-  * after 100 steps: <= 3e-6 for FP32C.
+from the same FP32-rounded state), about three times the largest error
+observed over the fields and kernels on MI355X:
+  * 64^3, after 1 step: <= 1.5e-7 (observed 4.8e-8: the result is stored
+    to FP32 once, half an ulp, 3e-8 of the field's largest value, plus the
+    FP32 first derivatives).
+  * 64^3, after 100 steps: <= 3.5e-7 for FP32C (observed 1.1e-7), <= 2e-5
+    for plain FP32 (observed 6.7e-6).
+  * 512^3, one step at sampled cells against the oracle run on the
+    unrounded state: <= 7.5e-7 (observed 2.4e-7 in u: at this spacing the
+    Lorentz force takes second differences of the FP32 rounding of A,
+    amplified by 1/h^2).
 The Kahan pin: a uniform state in a uniform external field has a constant
 induction term, so A_x grows by dt*(u x B)_x per step; with increments far
 below one FP32 ulp, FP32C tracks the exact sum to an ulp while plain FP32
@@ -61,16 +67,16 @@ def test_f32c_against_oracle_64(mhd, kernel):
     got1 = _run(mhd, f0, n, "f32c", wl["dt"], 1, kernel)
     e1 = [oracle.rel_err(got1[q], ref1[q]) for q in range(8)]
     say(f"f32c {kernel} 1 step:", ["%.2e" % e for e in e1])
-    assert max(e1) <= 1e-6
+    assert max(e1) <= 1.5e-7
     ref100 = oracle.step(f0, wl["dt"], p, 100)
     got100 = _run(mhd, f0, n, "f32c", wl["dt"], 100, kernel)
     e100 = [oracle.rel_err(got100[q], ref100[q]) for q in range(8)]
     say(f"f32c {kernel} 100 steps:", ["%.2e" % e for e in e100])
-    assert max(e100) <= 3e-6
+    assert max(e100) <= 3.5e-7
     plain = _run(mhd, f0, n, "f32", wl["dt"], 100, kernel)
     ep = [oracle.rel_err(plain[q], ref100[q]) for q in range(8)]
     say(f"f32 (plain) {kernel} 100 steps:", ["%.2e" % e for e in ep])
-    assert max(ep) <= 1e-4
+    assert max(ep) <= 2e-5
 
 
 @pytest.mark.parametrize("kernel", ["tiled", "split", "direct"])
@@ -113,4 +119,4 @@ def test_f32c_512_sampled_against_oracle(mhd, kernel):
     S.close()
     errs = [float(np.max(np.abs(got[q] - fs[2, q])) / scale[q]) for q in range(8)]
     say(f"f32c {kernel} vs oracle at 512^3 sampled, 1 step:", ["%.2e" % e for e in errs])
-    assert max(errs) <= 1e-6
+    assert max(errs) <= 7.5e-7

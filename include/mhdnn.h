@@ -81,6 +81,25 @@ int mhdnn_conv3d_wgrad(const uint16_t *x, const uint16_t *dz, int32_t n, int32_t
                        int32_t cin, int32_t cout, float *workspace, float *dw, float *db,
                        void *stream);
 
+/* mhdnn_conv3d_wgrad for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight training loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, bit for bit, with the per-block
+ * partial sums in a library-owned device array of
+ * MHDNN_WGRAD_SCRATCH_FLOATS floats (the partials of 512 blocks, 56.7 MB;
+ * each GPU keeps its own copy until the process ends) instead of a caller
+ * workspace.  Allocates nothing.  Sizes whose
+ * mhdnn_wgrad_workspace_floats(n, batch) exceeds MHDNN_WGRAD_SCRATCH_FLOATS
+ * are rejected with MHD_ERR_INVALID: every batch up to 32 at n = 64, up to
+ * 128 at n = 32 and up to 512 at n = 16 fits, larger ones do not.  All
+ * calls on one GPU share that array: calls that overlap in time on one GPU
+ * (other streams, other threads) race and must be serialised by the
+ * caller.
+ * Errors: MHD_ERR_INVALID (as mhdnn_conv3d_wgrad, and the size limit),
+ * MHD_ERR_NO_DEVICE, MHD_ERR_DEVICE. */
+#define MHDNN_WGRAD_SCRATCH_FLOATS (512LL * (27 * 32 * 32 + 32))
+int mhdnn_conv3d_wgrad_noalloc(const uint16_t *x, const uint16_t *dz, int32_t n, int32_t batch,
+                               int32_t cin, int32_t cout, float *dw, float *db, void *stream);
+
 /* From FP32 master weights w[cout][27][cin], write the BF16 kernel layouts:
  * w_pad[32][27][cin] (zero rows for o >= cout) and, if wt_pad is not NULL,
  * wt_pad[32][27][cout] with wt_pad[c][t][o] = w[o][26 - t][c] (rows c >= cin zero). */

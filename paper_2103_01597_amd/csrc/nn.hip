@@ -27,6 +27,8 @@
 // MFMA lane layout (32x32x16): lane l holds A row l%32 and B column l%32 at
 // K = 8(l/32)..8(l/32)+7; accumulator r of lane l is D[8(r/4) + 4(l/32) +
 // r%4][l%32].
+#include <mutex>
+
 #include "mhd_internal.hpp"
 #include "../../include/mhdnn.h"
 
@@ -808,6 +810,37 @@ hipError_t launch_wgrad(const uint16_t* x, const uint16_t* dz, int n, int batch,
 }  // namespace
 }  // namespace mhd
 
+// ------------------------------------------------------ no-alloc wgrad
+// Workspace of mhdnn_conv3d_wgrad_noalloc: a file-scope device array (each
+// GPU the library runs on holds its own copy until the process ends).  Its
+// device address is looked up once per device, with that device current,
+// and only that address is ever handed to a kernel.  Every partial the
+// reduction reads is written by the weight-gradient kernel of the same
+// call, so nothing needs clearing between calls.
+static __device__ __align__(256) float scratch[MHDNN_WGRAD_SCRATCH_FLOATS];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex scratch_mutex;
+float* scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+int scratch_of_current_device(float** out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return MHD_ERR_NO_DEVICE;
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return MHD_ERR_DEVICE;
+    std::lock_guard<std::mutex> lock(scratch_mutex);
+    if (!scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p)
+            return MHD_ERR_DEVICE;
+        scratch_ptr[dev] = static_cast<float*>(p);
+    }
+    *out = scratch_ptr[dev];
+    return MHD_OK;
+}
+}  // namespace
+
 using namespace mhd;
 
 extern "C" {
@@ -905,6 +938,26 @@ int mhdnn_conv3d_wgrad(const uint16_t* x, const uint16_t* dz, int32_t n, int32_t
     else if (cin == 32 && cout == 8) e = launch_wgrad<32, 8>(x, dz, n, batch, workspace, dw, db, st);
     else if (cin == 8 && cout == 8) e = launch_wgrad<8, 8>(x, dz, n, batch, workspace, dw, db, st);
     else return MHD_ERR_INVALID;
+    return status(e);
+}
+
+int mhdnn_conv3d_wgrad_noalloc(const uint16_t* x, const uint16_t* dz, int32_t n, int32_t batch,
+                               int32_t cin, int32_t cout, float* dw, float* db, void* stream)
+{
+    if (!x || !dz || !dw || !db || !conv_n_ok(n) || batch < 1 || batch > 65536)
+        return MHD_ERR_INVALID;
+    const bool shape_ok = (cin == 8 || cin == 32) && (cout == 8 || cout == 32);
+    if (!shape_ok || mhdnn_wgrad_workspace_floats(n, batch) > MHDNN_WGRAD_SCRATCH_FLOATS)
+        return MHD_ERR_INVALID;
+    float* ws = nullptr;
+    const int rc = scratch_of_current_device(&ws);
+    if (rc != MHD_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    if (cin == 8 && cout == 32) e = launch_wgrad<8, 32>(x, dz, n, batch, ws, dw, db, st);
+    else if (cin == 32 && cout == 32) e = launch_wgrad<32, 32>(x, dz, n, batch, ws, dw, db, st);
+    else if (cin == 32 && cout == 8) e = launch_wgrad<32, 8>(x, dz, n, batch, ws, dw, db, st);
+    else e = launch_wgrad<8, 8>(x, dz, n, batch, ws, dw, db, st);
     return status(e);
 }
 

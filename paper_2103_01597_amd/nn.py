@@ -16,7 +16,7 @@ from . import mhd as _mhd
 EXPORTS = ("mhdnn_box_filter4", "mhdnn_pack", "mhdnn_conv3d_fwd", "mhdnn_conv3d_dgrad",
            "mhdnn_wgrad_workspace_floats", "mhdnn_conv3d_wgrad", "mhdnn_prepare_weights",
            "mhdnn_mse", "mhdnn_pair", "mhdnn_field_stats_workspace_doubles",
-           "mhdnn_field_stats", "mhdnn_adam", "mhdnn_apply")
+           "mhdnn_field_stats", "mhdnn_adam", "mhdnn_apply", "mhdnn_conv3d_wgrad_noalloc")
 _INT64_RESULT = ("mhdnn_wgrad_workspace_floats", "mhdnn_field_stats_workspace_doubles")
 LAYERS = ((8, 32, True), (32, 32, True), (32, 8, False))  # (cin, cout, gelu)
 
@@ -37,6 +37,7 @@ def lib():
     L.mhdnn_wgrad_workspace_floats.argtypes = [i32, i32]
     L.mhdnn_wgrad_workspace_floats.restype = i64
     L.mhdnn_conv3d_wgrad.argtypes = [vp, vp, i32, i32, i32, i32, vp, vp, vp, vp]
+    L.mhdnn_conv3d_wgrad_noalloc.argtypes = [vp, vp, i32, i32, i32, i32, vp, vp, vp]
     L.mhdnn_prepare_weights.argtypes = [vp, i32, i32, vp, vp, vp]
     L.mhdnn_mse.argtypes = [vp, vp, fp, i32, i32, vp, vp, vp]
     L.mhdnn_pair.argtypes = [vp, vp, vp, vp, vp, vp, vp]

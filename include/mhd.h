@@ -228,8 +228,8 @@ int mhd_rk3_substep_box(mhd_ctx *ctx, int32_t s, const mhd_box *box, const void 
 /* mhd_step with the segmented iteration.  Per substep: the boundary
  * segments of the input are packed on `stream`; the exchange and unpack
  * (as mhd_halo_exchange_self) run on `comm_stream` while the inner box is
- * updated on `stream`; the six outer slabs follow on `stream` once the halo
- * is in.  The inner box keeps r cells from the z faces, 32 from the x faces
+ * updated on `stream`; the six outer slabs follow on `stream`, in one launch,
+ * once the halo is in.  The inner box keeps r cells from the z faces, 32 from the x faces
  * and 8 from the y faces (whole tiles of the fused kernels); on return all
  * work of `comm_stream` is ordered before the rest of `stream`.  Results are
  * identical to mhd_step's, bit for bit.  sendbuf, recvbuf: device buffers of

@@ -143,9 +143,15 @@ int mhdnn_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr
 /* Add a network correction to the interior of a coarse solver state:
  * f[q][cell] += y[cell][q] * scale[q] (scale: 8 host floats), with the
  * compensated update of the FP32C variant when `comp` is not NULL.  `ctx`
- * is the coarse solver context (FP32 storage). */
+ * is the coarse solver context (FP32 storage).
+ * `guard` (device, 2 int32, may be NULL) makes the plain method the
+ * fallback without a host round trip: the correction is applied only if
+ * every corrected value (and compensation) of the call is finite, else the
+ * state is left as the plain step left it and guard[1] is incremented
+ * (the number of refused corrections; the caller zeroes it once).  guard[0]
+ * is working space of the call.  Calls sharing a guard must not overlap. */
 int mhdnn_apply(const void *ctx, void *fields, void *comp, const float *y, const float *scale,
-                void *stream);
+                int32_t *guard, void *stream);
 
 #ifdef __cplusplus
 }

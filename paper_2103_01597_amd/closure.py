@@ -21,8 +21,9 @@ reconstruction of turbulent flow only as related work, Section 6):
   f <- Step_c(f) + y * std_D (``mhdnn_apply``, compensated).
 * judged against the plain coarse run by the relative L2 error to the
   filtered truth and by shell spectra of kinetic and magnetic energy.
-The plain method stays the fallback: ``corrected_run`` returns the plain
-trajectory's state whenever the network output is non-finite.
+The plain method stays the fallback: in ``CoarseRun`` a step whose corrected
+state would not be finite keeps the plain step's state (a device-side guard
+in ``mhdnn_apply``).
 """
 from __future__ import annotations
 
@@ -45,7 +46,7 @@ def _to_coarse_solver(S, coarse_flat, buf):
     S.halo_periodic(buf)
 
 
-def generate_pairs(n_fine=256, runs=10, pairs_per_run=200, seed_base=5000, kmax=8,
+def generate_pairs(n_fine=256, runs=40, pairs_per_run=50, seed_base=5000, kmax=8,
                    amp=(0.0, 0.1, 0.1, 0.1, 0.0, 1e-2, 1e-2, 1e-2), dt_fine=1e-3, ratio=4,
                    fine_prec="f64", log=None):
     """Returns (X, D, C0s): coarse-step tendencies and targets, FP32
@@ -141,12 +142,60 @@ def _rel_l2(a, b):
             for q in range(8)]
 
 
+class CoarseRun:
+    """A coarse FP32C run of the method, plain or with the closure added
+    after every step.  The correction is guarded on the device
+    (``mhdnn_apply`` with a guard): a step whose corrected state would not be
+    finite keeps the plain step's state, with no host round trip; the number
+    of such refusals is read once, at the end (``fallbacks``)."""
+
+    def __init__(self, nc, trained=None, lengths=None):
+        import torch
+        self.S = _solver(nc, "f32c", lengths)
+        self.nc, self.trained = nc, trained
+        self.cb = [self.S.empty(), self.S.empty()]
+        self.w, self.comp = self.S.zeros(), self.S.zeros()
+        self.c = 0
+        if trained is not None:
+            self.prev = self.S.empty()
+            self.xb = torch.empty(nc ** 3 * 8, dtype=torch.bfloat16, device="cuda")
+            self.guard = torch.zeros(2, dtype=torch.int32, device="cuda")
+
+    def reset(self, coarse_flat):
+        _to_coarse_solver(self.S, coarse_flat, self.cb[0])
+        self.comp.zero_()
+        self.c = 0
+        if self.trained is not None:
+            self.guard.zero_()
+
+    def step(self, dt):
+        """One coarse step (plus the correction); asynchronous."""
+        S, t = self.S, self.trained
+        if t is not None:
+            self.prev.copy_(self.cb[self.c])
+        self.c = S.step(self.cb, self.c, self.w, self.comp, dt, 1)
+        if t is not None:
+            nn.pack_solver(S, self.cb[self.c], t.mean, t.inv_std, self.xb, sub=self.prev)
+            y, _ = t.net.forward(self.xb, self.nc, 1)
+            nn.apply(S, self.cb[self.c], self.comp, y, t.dscale, guard=self.guard)
+
+    def state(self):
+        return self.S.interior_view(self.cb[self.c])
+
+    def fallbacks(self):
+        return 0 if self.trained is None else int(self.guard[1].item())
+
+    def close(self):
+        self.S.close()
+
+
 def evaluate(trained, n_fine=256, seed=9000, steps=50, kmax=8,
              amp=(0.0, 0.1, 0.1, 0.1, 0.0, 1e-2, 1e-2, 1e-2), dt_fine=1e-3, ratio=4,
-             fine_prec="f64"):
+             fine_prec="f64", return_truth=False):
     """Held-out run: filtered fine truth vs plain coarse vs corrected coarse.
     Returns per-step relative L2 errors (plain, corrected) per field and the
-    final states (truth, plain, corrected) as host arrays."""
+    final states (truth, plain, corrected) as host arrays (and, with
+    return_truth, the filtered truth of every step on the device)."""
     import torch
     nc = n_fine // 4
     F = _solver(n_fine, fine_prec)
@@ -163,38 +212,21 @@ def evaluate(trained, n_fine=256, seed=9000, steps=50, kmax=8,
             cur = F.step(fb, cur, wf, compf, dt_fine, ratio)
     F.close()
     del fb, wf
-    Sc = _solver(nc, "f32c")
     res = {}
     for mode in ("plain", "corrected"):
-        cb = [Sc.empty(), Sc.empty()]
-        wc, comp = Sc.zeros(), Sc.zeros()
-        _to_coarse_solver(Sc, truth[0], cb[0])
-        c = 0
+        run = CoarseRun(nc, trained if mode == "corrected" else None)
+        run.reset(truth[0])
         errs = []
-        xb = torch.empty(nc ** 3 * 8, dtype=torch.bfloat16, device="cuda")
-        prev, plain_state, plain_comp = Sc.empty(), Sc.empty(), Sc.empty()
-        fallbacks = 0
         for i in range(steps):
-            if mode == "corrected":
-                prev.copy_(cb[c])
-            c = Sc.step(cb, c, wc, comp, ratio * dt_fine, 1)
-            if mode == "corrected":
-                nn.pack_solver(Sc, cb[c], trained.mean, trained.inv_std, xb, sub=prev)
-                y, _ = trained.net.forward(xb, nc, 1)
-                plain_state.copy_(cb[c])
-                plain_comp.copy_(comp)
-                nn.apply(Sc, cb[c], comp, y, trained.dscale)
-                if sum(Sc.reduce(cb[c], q, "nonfinite") for q in range(8)) > 0:
-                    # the plain method is the fallback
-                    cb[c].copy_(plain_state)
-                    comp.copy_(plain_comp)
-                    fallbacks += 1
-            st = Sc.interior_view(cb[c]).reshape(8, -1)
-            errs.append(_rel_l2(st, truth[i + 1].view(8, -1)))
-        res[mode] = (np.array(errs), Sc.download(cb[c]))
+            run.step(ratio * dt_fine)
+            errs.append(_rel_l2(run.state().reshape(8, -1), truth[i + 1].view(8, -1)))
+        res[mode] = (np.array(errs), run.state().double().cpu().numpy(), run.fallbacks())
+        run.close()
     final_truth = truth[steps].view(8, nc, nc, nc).double().cpu().numpy()
-    Sc.close()
-    return res["plain"][0], res["corrected"][0], final_truth, res["plain"][1], res["corrected"][1]
+    out = (res["plain"][0], res["corrected"][0], final_truth, res["plain"][1], res["corrected"][1])
+    if return_truth:
+        return out + (truth, res["corrected"][2])
+    return out
 
 
 def shell_spectra(state, lengths=(2 * math.pi,) * 3):

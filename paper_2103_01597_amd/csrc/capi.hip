@@ -13,12 +13,12 @@ namespace mhd {
 hipError_t launch_rk3_direct(const Grid& g, const Phys& P, int precision, const Box& bx, int s,
                              const void* f_in, void* f_out, void* w, void* comp, double dt,
                              hipStream_t st);
-hipError_t launch_rk3_tiled(const Grid& g, const Phys& P, int precision, const Box& bx, int s,
-                            const void* f_in, void* f_out, void* w, void* comp, double dt,
+hipError_t launch_rk3_tiled(const Grid& g, const Phys& P, int precision, const Box* bx, int nbox,
+                            int s, const void* f_in, void* f_out, void* w, void* comp, double dt,
                             hipStream_t st);
 hipError_t launch_rk3_split(const Grid& g, const Phys& P, const Phys* P_dev, int precision,
-                            const Box& bx, int s, const void* f_in, void* f_out, void* w,
-                            void* comp, double dt, hipStream_t st);
+                            const Box* bx, int nbox, int s, const void* f_in, void* f_out,
+                            void* w, void* comp, double dt, hipStream_t st);
 }  // namespace mhd
 
 using namespace mhd;
@@ -94,26 +94,40 @@ void drop_graph(StepGraph& gr)
     gr = StepGraph{};
 }
 
-int one_substep(mhd_ctx* ctx, int s, const Box& bx, const void* f_in, void* f_out, void* w,
-                void* comp, double dt, hipStream_t st)
+// One launch of the fused kernel over up to six disjoint boxes (the direct
+// kernel: one launch per box); empty boxes are dropped.
+int one_substep(mhd_ctx* ctx, int s, const Box* boxes, int nbox, const void* f_in, void* f_out,
+                void* w, void* comp, double dt, hipStream_t st)
 {
-    if (bx.x1 <= bx.x0 || bx.y1 <= bx.y0 || bx.z1 <= bx.z0) return MHD_OK;  // empty box
+    Box bx[6];
+    int n = 0;
+    for (int k = 0; k < nbox && n < 6; ++k)
+        if (boxes[k].x1 > boxes[k].x0 && boxes[k].y1 > boxes[k].y0 && boxes[k].z1 > boxes[k].z0)
+            bx[n++] = boxes[k];
+    if (n == 0) return MHD_OK;
     const Grid& g = ctx->grid;
     const int prec = ctx->cfg.precision;
-    hipError_t e;
+    hipError_t e = hipSuccess;
     switch (ctx->cfg.kernel) {
     case MHD_KERNEL_TILED:
-        e = launch_rk3_tiled(g, ctx->phys, prec, bx, s, f_in, f_out, w, comp, dt, st);
+        e = launch_rk3_tiled(g, ctx->phys, prec, bx, n, s, f_in, f_out, w, comp, dt, st);
         break;
     case MHD_KERNEL_SPLIT:
-        e = launch_rk3_split(g, ctx->phys, ctx->phys_dev, prec, bx, s, f_in, f_out, w, comp, dt,
-                             st);
+        e = launch_rk3_split(g, ctx->phys, ctx->phys_dev, prec, bx, n, s, f_in, f_out, w, comp,
+                             dt, st);
         break;
     default:
-        e = launch_rk3_direct(g, ctx->phys, prec, bx, s, f_in, f_out, w, comp, dt, st);
+        for (int k = 0; k < n && e == hipSuccess; ++k)
+            e = launch_rk3_direct(g, ctx->phys, prec, bx[k], s, f_in, f_out, w, comp, dt, st);
         break;
     }
     return from_hip(e);
+}
+
+int one_substep(mhd_ctx* ctx, int s, const Box& bx, const void* f_in, void* f_out, void* w,
+                void* comp, double dt, hipStream_t st)
+{
+    return one_substep(ctx, s, &bx, 1, f_in, f_out, w, comp, dt, st);
 }
 
 int one_substep(mhd_ctx* ctx, int s, const void* f_in, void* f_out, void* w, void* comp,
@@ -495,10 +509,8 @@ int mhd_step_segmented(mhd_ctx* ctx, void* const f[2], int32_t* cur, void* w, vo
             if (rc != MHD_OK) return rc;
             e = hipStreamWaitEvent(st, ctx->ev_halo, 0);
             if (e != hipSuccess) return from_hip(e);
-            for (const Box& b : outer) {
-                rc = one_substep(ctx, s, b, f[c], f[1 - c], w, comp, dt, st);
-                if (rc != MHD_OK) return rc;
-            }
+            rc = one_substep(ctx, s, outer, 6, f[c], f[1 - c], w, comp, dt, st);
+            if (rc != MHD_OK) return rc;
             c ^= 1;
         }
         *cur = c;

@@ -1,16 +1,8 @@
 // Periodic halo fill (Section 3.3): every halo cell of the padded grid
 // takes the interior cell given by the mapping s' = ((s - r) mod n) + r on
-// each axis.  One launch fills sides, edges and corners of all 8 fields:
-// each halo cell reads its interior source directly, so no cell depends on
-// another halo cell and the three regions below can run concurrently.
-//
-//   region Z: the 2r halo planes z < r, z >= nz+r     (all y, all x)
-//   region Y: interior planes, the 2r halo rows of y  (all x)
-//   region X: interior planes and rows, the 2r halo columns of x
-//
-// r is the halo width (the stencil radius, 1..4).  Regions Z and Y are
-// contiguous runs of x and coalesce; region X touches 2r elements per row.
-// Bytes per launch: 2 * 8 * elem * (M^3 - N^3).
+// each axis, r the halo width (the stencil radius, 1..4); sides, edges and
+// corners of all 8 fields are filled.  Bytes per fill: 2 * 8 * elem *
+// (M^3 - N^3).
 #include "mhd_internal.hpp"
 
 namespace mhd {
@@ -22,61 +14,92 @@ __device__ __forceinline__ int wrap_index(int s, int n, int r)
     return (t < 0 ? t + n : t) + r;
 }
 
+// Three launches, each reading only cells that are final when it runs:
+//   X: interior planes and rows, the 2r halo columns (element copies of
+//      interior cells, x wrapped);
+//   Y: interior planes, the 2r halo rows, each copied whole (its halo
+//      columns included, filled by X) from the wrapped interior row;
+//   Z: the 2r halo planes, each copied whole from the wrapped interior plane.
+// Y and Z copy whole rows and planes in units of V elements (V = 2 when the
+// padded row length mx is even: every row then starts on a V-element
+// boundary, so FP64 moves 16 bytes per access).
+template <typename E, int V>
+struct alignas(sizeof(E) * V) HVec {
+    E v[V];
+};
+
 template <typename E>
-__global__ __launch_bounds__(256) void k_halo(Grid g, E* __restrict__ fields)
+__global__ __launch_bounds__(256) void k_halo_x(Grid g, E* __restrict__ fields)
 {
     const int r = g.r, w = 2 * g.r;
-    const int per_field_z = w * g.mxy;
-    const int per_field_y = g.nz * w * g.mx;
-    const int per_field_x = g.nz * g.ny * w;
-    const int total = per_field_z + per_field_y + per_field_x;
-    const int t0 = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t0 >= total)
-        return;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= g.nz * g.ny * w) return;
     E* f = fields + (int64_t)blockIdx.y * g.fstride;
+    const int cols = w * g.ny;
+    const int zz = t / cols, rem = t - zz * cols;
+    const int yy = rem / w, c = rem - yy * w;
+    const int x = c < r ? c : g.nx + c;
+    const int row = ((r + zz) * g.my + r + yy) * g.mx;
+    f[row + x] = f[row + wrap_index(x, g.nx, r)];
+}
 
-    int x, y, z, t = t0;
-    if (t < per_field_z) {
-        const int p = t / g.mxy;
-        const int rem = t - p * g.mxy;
-        y = rem / g.mx;
-        x = rem - y * g.mx;
-        z = p < r ? p : g.nz + p;
-    } else if ((t -= per_field_z) < per_field_y) {
-        const int rows = w * g.mx;
-        const int zz = t / rows;
-        const int rem = t - zz * rows;
-        const int yr = rem / g.mx;
-        x = rem - yr * g.mx;
-        y = yr < r ? yr : g.ny + yr;
-        z = r + zz;
-    } else {
-        t -= per_field_y;
-        const int cols = w * g.ny;
-        const int zz = t / cols;
-        const int rem = t - zz * cols;
-        const int yy = rem / w;
-        const int c = rem - yy * w;
-        x = c < r ? c : g.nx + c;
-        y = r + yy;
-        z = r + zz;
-    }
-    const int sx = wrap_index(x, g.nx, r), sy = wrap_index(y, g.ny, r), sz = wrap_index(z, g.nz, r);
-    f[(z * g.my + y) * g.mx + x] = f[(sz * g.my + sy) * g.mx + sx];
+template <typename E, int V>
+__global__ __launch_bounds__(256) void k_halo_y(Grid g, E* __restrict__ fields)
+{
+    using Vt = HVec<E, V>;
+    const int r = g.r, row_units = g.mx / V;
+    const int per_plane = 2 * r * row_units;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= g.nz * per_plane) return;
+    E* f = fields + (int64_t)blockIdx.y * g.fstride;
+    const int zz = t / per_plane, rem = t - zz * per_plane;
+    const int yr = rem / row_units, u = rem - yr * row_units;
+    const int y = yr < r ? yr : g.ny + yr;
+    const int plane = (r + zz) * g.mxy;
+    Vt* dst = reinterpret_cast<Vt*>(f + plane + y * g.mx);
+    const Vt* src = reinterpret_cast<const Vt*>(f + plane + wrap_index(y, g.ny, r) * g.mx);
+    dst[u] = src[u];
+}
+
+template <typename E, int V>
+__global__ __launch_bounds__(256) void k_halo_z(Grid g, E* __restrict__ fields)
+{
+    using Vt = HVec<E, V>;
+    const int r = g.r, plane_units = g.mxy / V;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * r * plane_units) return;
+    E* f = fields + (int64_t)blockIdx.y * g.fstride;
+    const int p = t / plane_units, u = t - p * plane_units;
+    const int z = p < r ? p : g.nz + p;
+    Vt* dst = reinterpret_cast<Vt*>(f + z * g.mxy);
+    const Vt* src = reinterpret_cast<const Vt*>(f + wrap_index(z, g.nz, r) * g.mxy);
+    dst[u] = src[u];
+}
+
+template <typename E, int V>
+void launch_halo_typed(const Grid& g, void* fields, hipStream_t st)
+{
+    const int w = 2 * g.r;
+    auto blocks = [](int n) { return dim3((unsigned)((n + 255) / 256), NQ); };
+    hipLaunchKernelGGL(k_halo_x<E>, blocks(g.nz * g.ny * w), dim3(256), 0, st, g, (E*)fields);
+    hipLaunchKernelGGL((k_halo_y<E, V>), blocks(g.nz * w * (g.mx / V)), dim3(256), 0, st, g,
+                       (E*)fields);
+    hipLaunchKernelGGL((k_halo_z<E, V>), blocks(w * (g.mxy / V)), dim3(256), 0, st, g,
+                       (E*)fields);
 }
 
 }  // namespace
 
 hipError_t launch_halo(const Grid& g, void* fields, int elem_size, hipStream_t st)
 {
-    const int w = 2 * g.r;
-    const int total = w * g.mxy + g.nz * w * g.mx + g.nz * g.ny * w;
-    dim3 block(256);
-    dim3 grid((total + 255) / 256, NQ);
-    if (elem_size == 8)
-        hipLaunchKernelGGL(k_halo<uint64_t>, grid, block, 0, st, g, (uint64_t*)fields);
-    else
-        hipLaunchKernelGGL(k_halo<uint32_t>, grid, block, 0, st, g, (uint32_t*)fields);
+    const bool vec = g.mx % 2 == 0;
+    if (elem_size == 8) {
+        if (vec) launch_halo_typed<uint64_t, 2>(g, fields, st);
+        else launch_halo_typed<uint64_t, 1>(g, fields, st);
+    } else {
+        if (vec) launch_halo_typed<uint32_t, 2>(g, fields, st);
+        else launch_halo_typed<uint32_t, 1>(g, fields, st);
+    }
     return hipGetLastError();
 }
 

@@ -299,6 +299,112 @@ __global__ __launch_bounds__(CONV_THR) void k_conv(const uint16_t* __restrict__ 
     }
 }
 
+// Output layer with 8 output channels (32 input channels): the same slab
+// march as k_conv, on the 16 x 16 x 32 BF16 MFMA, whose N of 16 pads the
+// 8 output channels half as much as the 32 x 32 x 16 shape's N of 32 (and
+// whose K of 32 takes all input channels of a tap at once, so no wave pair
+// splits K).  Each wave owns 32 cells (two M tiles of 16).  Lane layout:
+// A[row l%16][k 8(l/16)..+7], B[k 8(l/16)..+7][col l%16], D[row 4(l/16)+i][col l%16].
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(CONV_THR) void k_conv_out8(const uint16_t* __restrict__ x,
+                                                       const uint16_t* __restrict__ w,
+                                                       const float* __restrict__ bias, int n,
+                                                       int logn, int nch, int zc,
+                                                       float* __restrict__ outf)
+{
+    extern __shared__ __align__(16) uint16_t sm[];
+    constexpr int CIN = 32, COUT = 8;
+    constexpr int CP = conv_cp<CIN>();
+    const int RY = CONV_CELLS >> logn;
+    const int slot = (RY + 2) * n * CP;
+    const int nv = (RY + 2) * n * CIN / 8;
+    uint16_t* lx = sm;  // [3][RY+2][n][CP]
+    const int slabs = n / RY;
+    const int col_id = blockIdx.x / nch, ch_id = blockIdx.x - col_id * nch;
+    const int b = col_id / slabs, y0 = (col_id - b * slabs) * RY;
+    const int z0 = ch_id * zc, nz = min(zc, n - z0);
+    const size_t n3 = (size_t)n * n * n;
+    const uint16_t* xb = x + (size_t)b * n3 * CIN;
+    const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63, q16 = l >> 4, c16 = l & 15;
+
+    // B fragments for the whole march: column c16 (output channel; rows
+    // o >= 8 of w_pad are zero), K chunk 8 q16 of every tap
+    bf16x8 bw[27];
+#pragma unroll
+    for (int t = 0; t < 27; ++t) bw[t] = frag(w + ((size_t)c16 * 27 + t) * 32 + 8 * q16);
+
+    constexpr int NL = conv_loads<CIN>(16) > conv_loads<CIN>(64) ? conv_loads<CIN>(16)
+                                                                    : conv_loads<CIN>(64);
+    u16x8 pre[NL];
+    auto load = [&](int z) {
+        const int zz = (z + n) & (n - 1);
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int i = tid + k * CONV_THR;
+            if (i < nv) {
+                const int e = i * 8, cell = e / CIN, ch = e - cell * CIN;
+                const int xx = cell & (n - 1), r = cell >> logn;
+                const int yy = (y0 - 1 + r + n) & (n - 1);
+                const size_t src = ((size_t)((zz << logn) + yy) << logn) + xx;
+                pre[k] = *reinterpret_cast<const u16x8*>(xb + src * CIN + ch);
+            }
+        }
+    };
+    auto store = [&](int sl) {
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int i = tid + k * CONV_THR;
+            if (i < nv) {
+                const int e = i * 8, cell = e / CIN, ch = e - cell * CIN;
+                *reinterpret_cast<u16x8*>(lx + sl * slot + cell * CP + ch) = pre[k];
+            }
+        }
+    };
+    load(z0 - 1);
+    store(0);
+    load(z0);
+    store(1);
+    load(z0 + 1);
+
+    int rr[2], xx[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int m = 32 * wv + 16 * j + c16;
+        rr[j] = m >> logn;
+        xx[j] = m & (n - 1);
+    }
+    const float bv = c16 < COUT ? bias[c16] : 0.0f;
+    for (int p = 0; p < nz; ++p) {
+        store((p + 2) % 3);  // plane z0+p+1 replaces plane z0+p-2
+        __syncthreads();
+        if (p + 1 < nz) load(z0 + p + 2);
+        const int sb[3] = {(p % 3) * (RY + 2), ((p + 1) % 3) * (RY + 2), ((p + 2) % 3) * (RY + 2)};
+        const size_t c0 = (size_t)b * n3 + ((size_t)(z0 + p) << (2 * logn)) + ((size_t)y0 << logn);
+        floatx4 acc[2] = {floatx4{}, floatx4{}};
+#pragma unroll
+        for (int t = 0; t < 27; ++t) {
+            const int dz = t / 9, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int s = (sb[dz] + rr[j] + dy + 1) * n + ((xx[j] + dx) & (n - 1));
+                const bf16x8 a = frag(lx + s * CP + 8 * q16);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[t], acc[j], 0, 0, 0);
+            }
+        }
+        if (c16 < COUT) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int cl = 32 * wv + 16 * j + 4 * q16 + i;
+                    outf[(c0 + cl) * COUT + c16] = acc[j][i] + bv;
+                }
+        }
+        __syncthreads();  // every read of plane z0+p-1 is done before it is replaced
+    }
+}
+
 // --------------------------------------------------------------- wgrad
 // Weight gradient dW[o][t][c] = sum over cells of dz[cell][o] x[cell + off(t)][c]
 // (and db[o] = sum dz[cell][o]) on the same slabs and z chunks as k_conv.
@@ -580,9 +686,44 @@ __global__ void k_pack(const float* __restrict__ src, const float* __restrict__ 
     reinterpret_cast<u16x8*>(out)[i] = v;
 }
 
-__global__ void k_apply(Grid g, float* __restrict__ f, float* __restrict__ comp,
-                        const float* __restrict__ y, Vec8 scale)
+// Guarded correction: guard[0] counts the cells whose corrected value
+// would not be finite (reset by k_guard_reset, filled by k_guard_check),
+// guard[1] the corrections refused so far.  k_apply then leaves the state
+// untouched when guard[0] != 0 -- the plain method's step stands.
+__global__ void k_guard_reset(int* __restrict__ guard)
 {
+    if (threadIdx.x == 0) guard[0] = 0;
+}
+
+__global__ void k_guard_check(Grid g, const float* __restrict__ f, const float* __restrict__ comp,
+                              const float* __restrict__ y, Vec8 scale, int* __restrict__ guard)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;  // interior cell, x fastest
+    const int n3 = g.nx * g.ny * g.nz;
+    bool bad = false;
+    if (i < n3) {
+        const int xx = i % g.nx, yy = (i / g.nx) % g.ny, zz = i / (g.nx * g.ny);
+        const int c = g.interior + zz * g.mxy + yy * g.mx + xx;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t o = q * g.fstride + c;
+            const float add = y[(int64_t)i * 8 + q] * scale.v[q];
+            float cc = comp ? comp[o] : 0.0f;
+            const float t = comp ? kahan_add(f[o], add, cc) : f[o] + add;
+            bad |= !isfinite(t) || !isfinite(cc);
+        }
+    }
+    const unsigned long long m = __ballot(bad);
+    if (m && (threadIdx.x & 63) == 0) atomicAdd(guard, __popcll(m));
+}
+
+__global__ void k_apply(Grid g, float* __restrict__ f, float* __restrict__ comp,
+                        const float* __restrict__ y, Vec8 scale, int* __restrict__ guard)
+{
+    if (guard && guard[0] != 0) {  // uniform over the launch
+        if (blockIdx.x == 0 && threadIdx.x == 0) guard[1] += 1;
+        return;
+    }
     const int i = blockIdx.x * blockDim.x + threadIdx.x;  // interior cell, x fastest
     const int n3 = g.nx * g.ny * g.nz;
     if (i >= n3) return;
@@ -780,6 +921,25 @@ hipError_t launch_conv(const uint16_t* x, const uint16_t* w, const float* bias, 
     return hipGetLastError();
 }
 
+hipError_t launch_conv_out8(const uint16_t* x, const uint16_t* w, const float* bias, int n,
+                            int batch, float* of, hipStream_t st)
+{
+    static bool attr = false;
+    if (!attr) {
+        const int most = (int)(conv_lds(32, 16) > conv_lds(32, 64) ? conv_lds(32, 16)
+                                                                   : conv_lds(32, 64));
+        hipError_t e = hipFuncSetAttribute((const void*)k_conv_out8,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, most);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    int columns, nch, zc;
+    conv_chunks(n, batch, columns, nch, zc);
+    hipLaunchKernelGGL(k_conv_out8, dim3(columns * nch), dim3(CONV_THR), conv_lds(32, n), st, x,
+                       w, bias, n, ilog2(n), nch, zc, of);
+    return hipGetLastError();
+}
+
 template <int CIN, int COUT>
 hipError_t launch_wgrad(const uint16_t* x, const uint16_t* dz, int n, int batch, float* ws,
                         float* dw, float* db, hipStream_t st)
@@ -895,6 +1055,8 @@ int mhdnn_conv3d_fwd(const uint16_t* x, const uint16_t* w_pad, const float* bias
                                            nullptr, st)
                       : launch_conv<8, 0>(x, w_pad, bias, nullptr, n, batch, cout, z_bf16, a_bf16,
                                           nullptr, st);
+    else if (cin == 32 && cout == 8)
+        e = launch_conv_out8(x, w_pad, bias, n, batch, y_f32, st);
     else
         e = cin == 32 ? launch_conv<32, 1>(x, w_pad, bias, nullptr, n, batch, cout, nullptr,
                                            nullptr, y_f32, st)
@@ -1029,7 +1191,7 @@ int mhdnn_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr
 }
 
 int mhdnn_apply(const void* ctx_, void* fields, void* comp, const float* y, const float* scale,
-                void* stream)
+                int32_t* guard, void* stream)
 {
     if (!ctx_ || !fields || !y || !scale) return MHD_ERR_INVALID;
     const mhd_ctx* ctx = (const mhd_ctx*)ctx_;
@@ -1038,8 +1200,15 @@ int mhdnn_apply(const void* ctx_, void* fields, void* comp, const float* y, cons
     Vec8 sc;
     for (int q = 0; q < 8; ++q) sc.v[q] = scale[q];
     const int n3 = g.nx * g.ny * g.nz;
-    hipLaunchKernelGGL(k_apply, dim3((n3 + 255) / 256), dim3(256), 0, (hipStream_t)stream, g,
-                       (float*)fields, (float*)comp, y, sc);
+    hipStream_t st = (hipStream_t)stream;
+    const dim3 grid((n3 + 255) / 256), block(256);
+    if (guard) {
+        hipLaunchKernelGGL(k_guard_reset, dim3(1), dim3(64), 0, st, (int*)guard);
+        hipLaunchKernelGGL(k_guard_check, grid, block, 0, st, g, (const float*)fields,
+                           (const float*)comp, y, sc, (int*)guard);
+    }
+    hipLaunchKernelGGL(k_apply, grid, block, 0, st, g, (float*)fields, (float*)comp, y, sc,
+                       (int*)guard);
     return status(hipGetLastError());
 }
 

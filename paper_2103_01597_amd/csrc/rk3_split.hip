@@ -39,8 +39,8 @@ namespace mhd {
 // rk3_split_dflt.hip (this file with MHD_DEFAULT_SCHED defined), which the
 // build compiles with the default instruction scheduler: the iterative ILP
 // scheduler this file is built with makes it slower (measured at 512^3).
-hipError_t launch_rk3_split_dflt(const Grid& g, const Phys& P, const Phys* P_dev, const Box& bx,
-                                 int s, const void* f_in, void* f_out, void* w, double dt,
+hipError_t launch_rk3_split_dflt(const Grid& g, const Phys& P, const Phys* P_dev, const Box* bx,
+                                 int nbox, int s, const void* f_in, void* f_out, void* w, double dt,
                                  hipStream_t st);
 
 namespace {
@@ -48,7 +48,6 @@ namespace {
 #ifndef MHD_SPLIT_TX
 #define MHD_SPLIT_TX 32
 #endif
-constexpr int TX = MHD_SPLIT_TX;
 constexpr int NXF = 10;            // values F hands to M
 constexpr int NXM = 7;             // values M hands to F
 // Per precision and stencil radius RAD: the tile plane of TX x TY cells
@@ -57,7 +56,9 @@ constexpr int NXM = 7;             // values M hands to F
 // RAD = 3) and the LDS ring of RAD + 1 such planes of all 8 fields.
 template <int PREC, int RAD>
 struct SRing {
-    static constexpr int TY = (PREC == MHD_F64 && RAD == 4 ? 128 : 256) / TX;
+    static constexpr bool SMALL = PREC == MHD_F64 && RAD == 4;
+    static constexpr int TX = MHD_SPLIT_TX;
+    static constexpr int TY = (SMALL ? 128 : 256) / TX;
     static constexpr int NC = TX * TY;   // cells per tile plane
     static constexpr int NTH = 2 * NC;   // threads: two groups of NC
     static constexpr int HX = TX + 2 * RAD, HY = TY + 2 * RAD, PLANE = HX * HY;
@@ -93,12 +94,6 @@ constexpr int blocks_per_cu() { return PREC == MHD_F64 ? 1 : MHD_SPLIT_F32_BLOCK
 static_assert(SRing<MHD_F64, 4>::NC % 64 == 0 && SRing<MHD_F32, 1>::NC % 64 == 0,
               "each group must be whole waves");
 
-struct TileMap {
-    int ntx, nty;
-    int nch, zc;  // z chunks per tile column, planes per chunk
-    int round;    // workgroups resident at once (0: plain order)
-};
-
 // Per-axis scale factors of the integer-weight stencils.
 // (Sized by the radius: the kernel keeps these in scalar registers, which
 // are scarce.)
@@ -111,59 +106,14 @@ struct Scales {
     double wyz[RAD];  // W2(r, m)/(4 DEN2 h_y h_z)
 };
 
-constexpr int NO_TILE = -1;
-
-// Z chunks: a launch lasts about (rounds of resident workgroups) x (planes
-// each workgroup marches, its 7 warm-up planes included).  A box with few
-// tile columns (a thin outer slab of the segmented iteration) or a tile count
-// just above a whole number of rounds marches in the z chunking of least
-// such cost, with chunks of at least ZCHUNK_MIN planes.
-constexpr int ZCHUNK_MIN = 16, WARM_PLANES = 7;
-inline void z_chunks(TileMap& m, int nzb)
-{
-    const int64_t cols = (int64_t)m.ntx * m.nty;
-    m.nch = 1;
-    m.zc = nzb;
-    if (cols <= 0 || m.round <= 0) return;
-    int64_t best = -1;
-    for (int want = 1; want == 1 || want <= nzb / ZCHUNK_MIN; ++want) {
-        const int zc = (nzb + want - 1) / want, nch = (nzb + zc - 1) / zc;
-        const int64_t cost = (nch * cols + m.round - 1) / m.round * (zc + WARM_PLANES);
-        if (best < 0 || cost < best) {
-            best = cost;
-            m.nch = nch;
-            m.zc = zc;
-        }
-    }
-}
-
-// Workgroup b -> tile, XCD-aware: within a round of `round` resident
-// workgroups, XCD k (which receives every 8th workgroup) gets a contiguous
-// run of tiles, so tiles sharing an L2 are spatial neighbours.
-__device__ __forceinline__ int tile_of_block(int b, const TileMap& m)
-{
-    const int tiles = m.ntx * m.nty * m.nch;
-    if (m.round <= 0 || (m.round & 7) != 0) return b < tiles ? b : NO_TILE;
-    const int r = b / m.round, w = b - r * m.round;
-    const int rem = min(tiles - r * m.round, m.round);
-    const int per = (rem + 7) >> 3;
-    const int k = w >> 3;
-    if (k >= per) return NO_TILE;
-    const int t = r * m.round + (w & 7) * per + k;
-    return t < r * m.round + rem ? t : NO_TILE;
-}
-
 template <int PREC, int RAD>
-__global__ __launch_bounds__((SRing<PREC, RAD>::NTH), blocks_per_cu<PREC>()) void k_rk3_split(Grid g, const Phys* P_dev, Scales<RAD> sc, TileMap map, int s,
+__global__ __launch_bounds__((SRing<PREC, RAD>::NTH), blocks_per_cu<PREC>()) void k_rk3_split(Grid g, const Phys* P_dev, Scales<RAD> sc, TilePlan plan, int s,
                                                      const typename Prec<PREC>::T* __restrict__ fin,
                                                      typename Prec<PREC>::T* __restrict__ fout,
                                                      typename Prec<PREC>::T* __restrict__ w,
                                                      typename Prec<PREC>::T* __restrict__ comp,
-                                                     double dt, Box box)
+                                                     double dt)
 {
-    // the box's bounds as plain scalars (a struct captured by the lambdas
-    // below costs registers)
-    const int bx0 = box.x0, bx1 = box.x1, by0 = box.y0, by1 = box.y1;
     using T = typename Prec<PREC>::T;
     using Rt = typename Prec<PREC>::Rt;
     using D2 = typename Prec<PREC>::D2;
@@ -176,12 +126,19 @@ __global__ __launch_bounds__((SRing<PREC, RAD>::NTH), blocks_per_cu<PREC>()) voi
     constexpr int HX = RG::HX, PLANE = RG::PLANE, SLOT = RG::SLOT;
     constexpr int NSLOT = RG::NSLOT, FULL = RG::FULL, EXTRA = RG::EXTRA;
 
-    const int tile = tile_of_block(blockIdx.x, map);
-    if (tile == NO_TILE) return;  // the whole workgroup exits together
+    const int tile_g = tile_of_block(blockIdx.x, plan.tiles, plan.round);
+    if (tile_g == NO_TILE) return;  // the whole workgroup exits together
+    // the tile's box, its bounds as plain scalars (a struct captured by the
+    // lambdas below costs registers) and its tile grid
+    int kx0, kx1, ky0, ky1, kz0, kz1, ntx, nty, zc, tile;
+    plan_box(plan, box_of_tile(tile_g, plan), tile_g, kx0, kx1, ky0, ky1, kz0, kz1, ntx, nty, zc,
+             tile);
+    const int bx0 = kx0, bx1 = kx1, by0 = ky0, by1 = ky1;
     // tile = (chunk * nty + ty) * ntx + tx; the chunk marches its own z range
-    const int per_chunk = map.ntx * map.nty, ch = tile / per_chunk, txy = tile - ch * per_chunk;
-    const int tx = txy % map.ntx, ty = txy / map.ntx;
-    const int bz0 = box.z0 + ch * map.zc, bz1 = min(bz0 + map.zc, box.z1);
+    const int per_chunk = ntx * nty, ch = tile / per_chunk, txy = tile - ch * per_chunk;
+    const int tx = txy % ntx, ty = txy / ntx;
+    const int bz0 = kz0 + ch * zc, bz1 = min(bz0 + zc, kz1);
+    constexpr int TX = RG::TX;
     const int x0 = bx0 + tx * TX, y0 = by0 + ty * TY;
     // group index, made visibly wave-uniform so that the two groups' code
     // paths (each with its own registers and the same barriers) are scalar
@@ -577,8 +534,9 @@ __global__ __launch_bounds__((SRing<PREC, RAD>::NTH), blocks_per_cu<PREC>()) voi
 }
 
 template <int PREC, int RAD>
-hipError_t launch_one(const Grid& g, const Phys& P, const Phys* P_dev, const Box& bx, int s,
-                      const void* f_in, void* f_out, void* w, void* comp, double dt, hipStream_t st)
+hipError_t launch_one(const Grid& g, const Phys& P, const Phys* P_dev, const Box* bx, int nbox,
+                      int s, const void* f_in, void* f_out, void* w, void* comp, double dt,
+                      hipStream_t st)
 {
     using T = typename Prec<PREC>::T;
     static int round = -1;  // resident workgroups per round on this device
@@ -597,11 +555,8 @@ hipError_t launch_one(const Grid& g, const Phys& P, const Phys* P_dev, const Box
         if (e != hipSuccess) return e;
         round = per_cu * cus;
     }
-    TileMap m;
-    m.ntx = (bx.x1 - bx.x0 + TX - 1) / TX;
-    m.nty = (bx.y1 - bx.y0 + SRing<PREC, RAD>::TY - 1) / SRing<PREC, RAD>::TY;
-    m.round = round;
-    z_chunks(m, bx.z1 - bx.z0);
+    const TilePlan plan =
+        plan_tiles(bx, nbox, SRing<PREC, RAD>::TX, SRing<PREC, RAD>::TY, round);
     Scales<RAD> sc{};
     for (int a = 0; a < 3; ++a) {
         sc.d1[a] = P.inv_h[a] / DEN1(RAD);
@@ -612,28 +567,30 @@ hipError_t launch_one(const Grid& g, const Phys& P, const Phys* P_dev, const Box
         sc.wxz[k - 1] = W2(RAD, k) * P.inv_h[0] * P.inv_h[2] / (4.0 * DEN2(RAD));
         sc.wyz[k - 1] = W2(RAD, k) * P.inv_h[1] * P.inv_h[2] / (4.0 * DEN2(RAD));
     }
-    const int tiles = m.ntx * m.nty * m.nch;
-    const int blocks = (round > 0 && (round & 7) == 0) ? (tiles + round - 1) / round * round : tiles;
-    hipLaunchKernelGGL((k_rk3_split<PREC, RAD>), dim3(blocks), dim3(SRing<PREC, RAD>::NTH), lds, st, g, P_dev, sc, m,
-                       s, (const T*)f_in, (T*)f_out, (T*)w, (T*)comp, dt, bx);
+    hipLaunchKernelGGL((k_rk3_split<PREC, RAD>), dim3(plan_blocks(plan)),
+                       dim3(SRing<PREC, RAD>::NTH), lds, st, g, P_dev, sc, plan, s,
+                       (const T*)f_in, (T*)f_out, (T*)w, (T*)comp, dt);
     return hipGetLastError();
 }
 
 template <int RAD>
 hipError_t launch_order(const Grid& g, const Phys& P, const Phys* P_dev, int precision,
-                        const Box& bx, int s, const void* f_in, void* f_out, void* w, void* comp,
-                        double dt, hipStream_t st)
+                        const Box* bx, int nbox, int s, const void* f_in, void* f_out, void* w,
+                        void* comp, double dt, hipStream_t st)
 {
     switch (precision) {
     case MHD_F64:
         static_assert(lds_bytes<MHD_F64, RAD>() <= 160 * 1024, "FP64 ring exceeds the LDS");
         if constexpr (RAD == 4)
-            return launch_rk3_split_dflt(g, P, P_dev, bx, s, f_in, f_out, w, dt, st);
+            return launch_rk3_split_dflt(g, P, P_dev, bx, nbox, s, f_in, f_out, w, dt, st);
         else
-            return launch_one<MHD_F64, RAD>(g, P, P_dev, bx, s, f_in, f_out, w, nullptr, dt, st);
+            return launch_one<MHD_F64, RAD>(g, P, P_dev, bx, nbox, s, f_in, f_out, w, nullptr, dt,
+                                            st);
     case MHD_F32C:
-        return launch_one<MHD_F32C, RAD>(g, P, P_dev, bx, s, f_in, f_out, w, comp, dt, st);
-    default: return launch_one<MHD_F32, RAD>(g, P, P_dev, bx, s, f_in, f_out, w, nullptr, dt, st);
+        return launch_one<MHD_F32C, RAD>(g, P, P_dev, bx, nbox, s, f_in, f_out, w, comp, dt, st);
+    default:
+        return launch_one<MHD_F32, RAD>(g, P, P_dev, bx, nbox, s, f_in, f_out, w, nullptr, dt,
+                                        st);
     }
 }
 
@@ -642,25 +599,26 @@ hipError_t launch_order(const Grid& g, const Phys& P, const Phys* P_dev, int pre
 #ifndef MHD_DEFAULT_SCHED
 // P (host copy) sets the stencil scales; P_dev (device copy of the same
 // values) is what the kernel's physics reads.  The stencil radius is the
-// grid's halo width g.r (1..4).
+// grid's halo width g.r (1..4).  One launch updates the nbox (1..MAX_BOXES)
+// disjoint, non-empty boxes bx.
 hipError_t launch_rk3_split(const Grid& g, const Phys& P, const Phys* P_dev, int precision,
-                            const Box& bx, int s, const void* f_in, void* f_out, void* w,
-                            void* comp, double dt, hipStream_t st)
+                            const Box* bx, int nbox, int s, const void* f_in, void* f_out,
+                            void* w, void* comp, double dt, hipStream_t st)
 {
     switch (g.r) {
-    case 1: return launch_order<1>(g, P, P_dev, precision, bx, s, f_in, f_out, w, comp, dt, st);
-    case 2: return launch_order<2>(g, P, P_dev, precision, bx, s, f_in, f_out, w, comp, dt, st);
-    case 3: return launch_order<3>(g, P, P_dev, precision, bx, s, f_in, f_out, w, comp, dt, st);
-    case 4: return launch_order<4>(g, P, P_dev, precision, bx, s, f_in, f_out, w, comp, dt, st);
+    case 1: return launch_order<1>(g, P, P_dev, precision, bx, nbox, s, f_in, f_out, w, comp, dt, st);
+    case 2: return launch_order<2>(g, P, P_dev, precision, bx, nbox, s, f_in, f_out, w, comp, dt, st);
+    case 3: return launch_order<3>(g, P, P_dev, precision, bx, nbox, s, f_in, f_out, w, comp, dt, st);
+    case 4: return launch_order<4>(g, P, P_dev, precision, bx, nbox, s, f_in, f_out, w, comp, dt, st);
     default: return hipErrorInvalidValue;
     }
 }
 #else
-hipError_t launch_rk3_split_dflt(const Grid& g, const Phys& P, const Phys* P_dev, const Box& bx,
-                                 int s, const void* f_in, void* f_out, void* w, double dt,
+hipError_t launch_rk3_split_dflt(const Grid& g, const Phys& P, const Phys* P_dev, const Box* bx,
+                                 int nbox, int s, const void* f_in, void* f_out, void* w, double dt,
                                  hipStream_t st)
 {
-    return launch_one<MHD_F64, 4>(g, P, P_dev, bx, s, f_in, f_out, w, nullptr, dt, st);
+    return launch_one<MHD_F64, 4>(g, P, P_dev, bx, nbox, s, f_in, f_out, w, nullptr, dt, st);
 }
 #endif
 

@@ -45,7 +45,7 @@ def lib():
     L.mhdnn_field_stats_workspace_doubles.restype = i64
     L.mhdnn_field_stats.argtypes = [vp, i64, i64, vp, vp, vp]
     L.mhdnn_adam.argtypes = [vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp]
-    L.mhdnn_apply.argtypes = [vp, vp, vp, vp, fp, vp]
+    L.mhdnn_apply.argtypes = [vp, vp, vp, vp, fp, vp, vp]
     for fn in EXPORTS:
         if fn not in _INT64_RESULT:
             getattr(L, fn).restype = ctypes.c_int
@@ -143,9 +143,10 @@ def adam(p, g, m, v, lr, t, b1=0.9, b2=0.999, eps=1e-8, stream=None):
                                         _st(stream)))
 
 
-def apply(solver, fields, comp, y, scale, stream=None):
+def apply(solver, fields, comp, y, scale, guard=None, stream=None):
+    """guard: optional int32 device tensor of 2 elements (see mhdnn.h)."""
     _chk("mhdnn_apply", lib().mhdnn_apply(solver._ctx, _p(fields), _p(comp), _p(y), _f8(scale),
-                                          _st(stream)))
+                                          _p(guard), _st(stream)))
 
 
 class Closure:

@@ -318,6 +318,25 @@ def test_mse_and_pack_and_apply_exact(nn):
     cc = ((tt - f0).astype(np.float32) - yc).astype(np.float32)
     assert np.array_equal(S.interior_view(buf).cpu().numpy(), tt)
     assert np.array_equal(S.interior_view(comp).cpu().numpy(), cc)
+    # guarded apply: a finite correction is applied exactly as above; one
+    # non-finite value anywhere leaves the state and compensation untouched
+    # and counts a refusal in guard[1]
+    guard = torch.zeros(2, dtype=torch.int32, device="cuda")
+    S.interior_view(buf).copy_(torch.from_numpy(f0))
+    S.interior_view(comp).copy_(torch.from_numpy(c0))
+    nn.apply(S, buf, comp, torch.from_numpy(yv).cuda(), scale, guard=guard)
+    torch.cuda.synchronize()
+    assert np.array_equal(S.interior_view(buf).cpu().numpy(), tt)
+    assert np.array_equal(S.interior_view(comp).cpu().numpy(), cc)
+    assert guard[1].item() == 0
+    for bad in (float("nan"), float("inf")):
+        yb = yv.copy()
+        yb[rng.integers(yb.size)] = bad
+        nn.apply(S, buf, comp, torch.from_numpy(yb).cuda(), scale, guard=guard)
+        torch.cuda.synchronize()
+        assert np.array_equal(S.interior_view(buf).cpu().numpy(), tt)
+        assert np.array_equal(S.interior_view(comp).cpu().numpy(), cc)
+    assert guard[1].item() == 2
 
 
 def test_pair_and_field_stats(nn):
@@ -369,20 +388,32 @@ def test_box_filter(nn, prec):
 
 def test_closure_gains_over_plain_coarse_run(nn):
     """Small-scale end-to-end check of the learned closure: fine 64^3 runs of
-    the method, 4x box-filtered to 16^3, train, then a held-out run.  Over
-    the held-out run the corrected coarse run must track the filtered truth
-    better than the plain coarse run (the fallback), on average over the 8
-    fields (per-field errors are printed)."""
+    the method (32 seeded runs, 30 pairs each), 4x box-filtered to 16^3,
+    trained, then a held-out run of 40 coarse steps judged field by field
+    against the plain coarse run (the fallback).  Observed on MI355X (ratio
+    corrected / plain of the relative L2 error to the filtered truth):
+    run means 0.23 (s) to 0.67 (ln rho, uy); the worst single step 1.26
+    (ln rho at the first step, where ln rho itself is still near zero)."""
     from paper_2103_01597_amd import closure
     kw = dict(n_fine=64, kmax=3, dt_fine=2e-3)
-    X, D, _ = closure.generate_pairs(runs=4, pairs_per_run=60, seed_base=100, log=say, **kw)
-    trained, hist = closure.train(X, D, 16, epochs=10, batch=4, lr=2e-3, log=say)
+    X, D, _ = closure.generate_pairs(runs=32, pairs_per_run=30, seed_base=100, **kw)
+    trained, hist = closure.train(X, D, 16, epochs=6, batch=4, lr=1e-3)
+    del X, D
     ep, ec, truth, plain, corr = closure.evaluate(trained, seed=1000, steps=40, **kw)
     for i in sorted({0, 1, 4, 9, 19, len(ep) - 1}):
         say(f"step {i + 1} rel L2 plain    :", " ".join("%.3e" % e for e in ep[i]))
         say(f"step {i + 1} rel L2 corrected:", " ".join("%.3e" % e for e in ec[i]))
-    say("run mean plain    :", " ".join("%.3e" % e for e in ep.mean(axis=0)))
-    say("run mean corrected:", " ".join("%.3e" % e for e in ec.mean(axis=0)))
+    mp, mc = ep.mean(axis=0), ec.mean(axis=0)
+    say("run mean ratio      :", " ".join("%.2f" % v for v in mc / mp))
+    say("worst step ratio    :", " ".join("%.2f" % v for v in (ec / ep).max(axis=0)))
     assert hist[-1] < hist[0]
     assert np.all(np.isfinite(ec))
-    assert np.mean(ec) < np.mean(ep)
+    # every field's error over the run goes down
+    assert np.all(mc < mp), mc / mp
+    # no field is worse than 1.5x the plain run's error at any step
+    assert np.all(ec <= 1.5 * ep), (ec / ep).max(axis=0)
+    # the velocity and vector-potential fields gain at least 25% on average,
+    # the entropy at least a factor 2
+    uA = [1, 2, 3, 5, 6, 7]
+    assert mc[uA].mean() < 0.75 * mp[uA].mean()
+    assert mc[4] < 0.5 * mp[4]

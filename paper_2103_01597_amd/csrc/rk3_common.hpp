@@ -307,6 +307,23 @@ __device__ __forceinline__ int tile_of_block(int b, int tiles, int round)
     return t < r * round + rem ? t : NO_TILE;
 }
 
+// One box's tile grid, as a single-box launch passes it.
+struct TileMap {
+    int ntx, nty;  // tiles per axis
+    int nch, zc;   // z chunks per tile column, planes per chunk
+    int round;     // workgroups resident at once (0: plain order)
+};
+
+__device__ __forceinline__ int tile_of_block(int b, const TileMap& m)
+{
+    return tile_of_block(b, m.ntx * m.nty * m.nch, m.round);
+}
+
+inline TileMap plan_map(const TilePlan& p)
+{
+    return TileMap{p.ntx[0], p.nty[0], p.nch[0], p.zc[0], p.round};
+}
+
 // The box of a tile (a uniform value: the whole workgroup agrees).
 __device__ __forceinline__ int box_of_tile(int tile, const TilePlan& p)
 {

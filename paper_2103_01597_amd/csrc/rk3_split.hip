@@ -106,14 +106,33 @@ struct Scales {
     double wyz[RAD];  // W2(r, m)/(4 DEN2 h_y h_z)
 };
 
-template <int PREC, int RAD>
-__global__ __launch_bounds__((SRing<PREC, RAD>::NTH), blocks_per_cu<PREC>()) void k_rk3_split(Grid g, const Phys* P_dev, Scales<RAD> sc, TilePlan plan, int s,
+// MULTI: the launch covers the several boxes of `plan` and each workgroup
+// takes its box and tile grid from there; otherwise one box, `box` and `map`
+// (a separate instantiation, so that the single-box march is compiled as if
+// the plan did not exist).
+template <int PREC, int RAD, bool MULTI>
+__global__ __launch_bounds__((SRing<PREC, RAD>::NTH), blocks_per_cu<PREC>()) void k_rk3_split(Grid g, const Phys* P_dev, Scales<RAD> sc, TileMap map, int s,
                                                      const typename Prec<PREC>::T* __restrict__ fin,
                                                      typename Prec<PREC>::T* __restrict__ fout,
                                                      typename Prec<PREC>::T* __restrict__ w,
                                                      typename Prec<PREC>::T* __restrict__ comp,
-                                                     double dt)
+                                                     double dt, Box box, TilePlan plan)
 {
+    int multi_tile = 0;
+    if constexpr (MULTI) {
+        const int tile_g = tile_of_block(blockIdx.x, plan.tiles, plan.round);
+        if (tile_g == NO_TILE) return;  // the whole workgroup exits together
+        int x0, x1, y0, y1, z0, z1, ntx, nty, zc;
+        plan_box(plan, box_of_tile(tile_g, plan), tile_g, x0, x1, y0, y1, z0, z1, ntx, nty, zc,
+                 multi_tile);
+        box = Box{x0, x1, y0, y1, z0, z1};
+        map.ntx = ntx;
+        map.nty = nty;
+        map.zc = zc;
+    }
+    // the box's bounds as plain scalars (a struct captured by the lambdas
+    // below costs registers)
+    const int bx0 = box.x0, bx1 = box.x1, by0 = box.y0, by1 = box.y1;
     using T = typename Prec<PREC>::T;
     using Rt = typename Prec<PREC>::Rt;
     using D2 = typename Prec<PREC>::D2;
@@ -126,18 +145,12 @@ __global__ __launch_bounds__((SRing<PREC, RAD>::NTH), blocks_per_cu<PREC>()) voi
     constexpr int HX = RG::HX, PLANE = RG::PLANE, SLOT = RG::SLOT;
     constexpr int NSLOT = RG::NSLOT, FULL = RG::FULL, EXTRA = RG::EXTRA;
 
-    const int tile_g = tile_of_block(blockIdx.x, plan.tiles, plan.round);
-    if (tile_g == NO_TILE) return;  // the whole workgroup exits together
-    // the tile's box, its bounds as plain scalars (a struct captured by the
-    // lambdas below costs registers) and its tile grid
-    int kx0, kx1, ky0, ky1, kz0, kz1, ntx, nty, zc, tile;
-    plan_box(plan, box_of_tile(tile_g, plan), tile_g, kx0, kx1, ky0, ky1, kz0, kz1, ntx, nty, zc,
-             tile);
-    const int bx0 = kx0, bx1 = kx1, by0 = ky0, by1 = ky1;
+    const int tile = MULTI ? multi_tile : tile_of_block(blockIdx.x, map);
+    if (tile == NO_TILE) return;  // the whole workgroup exits together
     // tile = (chunk * nty + ty) * ntx + tx; the chunk marches its own z range
-    const int per_chunk = ntx * nty, ch = tile / per_chunk, txy = tile - ch * per_chunk;
-    const int tx = txy % ntx, ty = txy / ntx;
-    const int bz0 = kz0 + ch * zc, bz1 = min(bz0 + zc, kz1);
+    const int per_chunk = map.ntx * map.nty, ch = tile / per_chunk, txy = tile - ch * per_chunk;
+    const int tx = txy % map.ntx, ty = txy / map.ntx;
+    const int bz0 = box.z0 + ch * map.zc, bz1 = min(bz0 + map.zc, box.z1);
     constexpr int TX = RG::TX;
     const int x0 = bx0 + tx * TX, y0 = by0 + ty * TY;
     // group index, made visibly wave-uniform so that the two groups' code
@@ -542,11 +555,14 @@ hipError_t launch_one(const Grid& g, const Phys& P, const Phys* P_dev, const Box
     static int round = -1;  // resident workgroups per round on this device
     constexpr size_t lds = lds_bytes<PREC, RAD>();
     if (round < 0) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_rk3_split<PREC, RAD>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_rk3_split<PREC, RAD, false>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_rk3_split<PREC, RAD, true>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         int per_cu = 0, dev = 0, cus = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rk3_split<PREC, RAD>,
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rk3_split<PREC, RAD, false>,
                                                          SRing<PREC, RAD>::NTH, lds);
         if (e != hipSuccess) return e;
         e = hipGetDevice(&dev);
@@ -567,9 +583,15 @@ hipError_t launch_one(const Grid& g, const Phys& P, const Phys* P_dev, const Box
         sc.wxz[k - 1] = W2(RAD, k) * P.inv_h[0] * P.inv_h[2] / (4.0 * DEN2(RAD));
         sc.wyz[k - 1] = W2(RAD, k) * P.inv_h[1] * P.inv_h[2] / (4.0 * DEN2(RAD));
     }
-    hipLaunchKernelGGL((k_rk3_split<PREC, RAD>), dim3(plan_blocks(plan)),
-                       dim3(SRing<PREC, RAD>::NTH), lds, st, g, P_dev, sc, plan, s,
-                       (const T*)f_in, (T*)f_out, (T*)w, (T*)comp, dt);
+    const dim3 grid(plan_blocks(plan)), block(SRing<PREC, RAD>::NTH);
+    if (nbox == 1)
+        hipLaunchKernelGGL((k_rk3_split<PREC, RAD, false>), grid, block, lds, st, g, P_dev, sc,
+                           plan_map(plan), s, (const T*)f_in, (T*)f_out, (T*)w, (T*)comp, dt,
+                           plan.box[0], TilePlan{});
+    else
+        hipLaunchKernelGGL((k_rk3_split<PREC, RAD, true>), grid, block, lds, st, g, P_dev, sc,
+                           TileMap{}, s, (const T*)f_in, (T*)f_out, (T*)w, (T*)comp, dt, Box{},
+                           plan);
     return hipGetLastError();
 }
 

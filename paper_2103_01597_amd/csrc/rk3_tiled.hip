@@ -95,14 +95,33 @@ struct Scales {
 template <int PREC>
 constexpr int blocks_per_cu() { return PREC == MHD_F64 ? 1 : MHD_TILED_F32_BLOCKS; }
 
-template <int PREC, int RAD>
-__global__ __launch_bounds__((Ring<PREC, RAD>::NT), blocks_per_cu<PREC>()) void k_rk3_tiled(Grid g, Phys P, Scales<RAD> sc, TilePlan plan, int s,
+// MULTI: the launch covers the several boxes of `plan` and each workgroup
+// takes its box and tile grid from there; otherwise one box, `box` and `map`
+// (a separate instantiation, so that the single-box march is compiled as if
+// the plan did not exist).
+template <int PREC, int RAD, bool MULTI>
+__global__ __launch_bounds__((Ring<PREC, RAD>::NT), blocks_per_cu<PREC>()) void k_rk3_tiled(Grid g, Phys P, Scales<RAD> sc, TileMap map, int s,
                                                      const typename Prec<PREC>::T* __restrict__ fin,
                                                      typename Prec<PREC>::T* __restrict__ fout,
                                                      typename Prec<PREC>::T* __restrict__ w,
                                                      typename Prec<PREC>::T* __restrict__ comp,
-                                                     double dt)
+                                                     double dt, Box box, TilePlan plan)
 {
+    int multi_tile = 0;
+    if constexpr (MULTI) {
+        const int tile_g = tile_of_block(blockIdx.x, plan.tiles, plan.round);
+        if (tile_g == NO_TILE) return;  // the whole workgroup exits together
+        int x0, x1, y0, y1, z0, z1, ntx, nty, zc;
+        plan_box(plan, box_of_tile(tile_g, plan), tile_g, x0, x1, y0, y1, z0, z1, ntx, nty, zc,
+                 multi_tile);
+        box = Box{x0, x1, y0, y1, z0, z1};
+        map.ntx = ntx;
+        map.nty = nty;
+        map.zc = zc;
+    }
+    // the box's bounds as plain scalars (a struct captured by the lambdas
+    // below costs registers)
+    const int bx0 = box.x0, bx1 = box.x1, by0 = box.y0, by1 = box.y1;
     using T = typename Prec<PREC>::T;
     using Rt = typename Prec<PREC>::Rt;
     using D2 = typename Prec<PREC>::D2;
@@ -112,18 +131,12 @@ __global__ __launch_bounds__((Ring<PREC, RAD>::NT), blocks_per_cu<PREC>()) void 
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* __restrict__ lds = reinterpret_cast<T*>(smem_raw);
 
-    const int tile_g = tile_of_block(blockIdx.x, plan.tiles, plan.round);
-    if (tile_g == NO_TILE) return;  // the whole workgroup exits together
-    // the tile's box, its bounds as plain scalars (a struct captured by the
-    // lambdas below costs registers) and its tile grid
-    int kx0, kx1, ky0, ky1, kz0, kz1, ntx, nty, zc, tile;
-    plan_box(plan, box_of_tile(tile_g, plan), tile_g, kx0, kx1, ky0, ky1, kz0, kz1, ntx, nty, zc,
-             tile);
-    const int bx0 = kx0, bx1 = kx1, by0 = ky0, by1 = ky1;
+    const int tile = MULTI ? multi_tile : tile_of_block(blockIdx.x, map);
+    if (tile == NO_TILE) return;  // the whole workgroup exits together
     // tile = (chunk * nty + ty) * ntx + tx; the chunk marches its own z range
-    const int per_chunk = ntx * nty, ch = tile / per_chunk, txy = tile - ch * per_chunk;
-    const int tx = txy % ntx, ty = txy / ntx;
-    const int bz0 = kz0 + ch * zc, bz1 = min(bz0 + zc, kz1);
+    const int per_chunk = map.ntx * map.nty, ch = tile / per_chunk, txy = tile - ch * per_chunk;
+    const int tx = txy % map.ntx, ty = txy / map.ntx;
+    const int bz0 = box.z0 + ch * map.zc, bz1 = min(bz0 + map.zc, box.z1);
     const int x0 = bx0 + tx * TX, y0 = by0 + ty * TY;
     const int tid = threadIdx.x, lx = tid % TX, ly = tid / TX;
     const bool active = (x0 + lx < bx1) && (y0 + ly < by1);
@@ -476,11 +489,15 @@ hipError_t launch_one(const Grid& g, const Phys& P, const Box* bx, int nbox, int
     constexpr size_t lds = lds_bytes<PREC, RAD>();
     constexpr int TY = Ring<PREC, RAD>::TY, NT = Ring<PREC, RAD>::NT;
     if (round < 0) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_rk3_tiled<PREC, RAD>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_rk3_tiled<PREC, RAD, false>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_rk3_tiled<PREC, RAD, true>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         int per_cu = 0, dev = 0, cus = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rk3_tiled<PREC, RAD>, NT, lds);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rk3_tiled<PREC, RAD, false>,
+                                                         NT, lds);
         if (e != hipSuccess) return e;
         e = hipGetDevice(&dev);
         if (e != hipSuccess) return e;
@@ -499,8 +516,14 @@ hipError_t launch_one(const Grid& g, const Phys& P, const Box* bx, int nbox, int
         sc.wxz[k - 1] = W2(RAD, k) * P.inv_h[0] * P.inv_h[2] / (4.0 * DEN2(RAD));
         sc.wyz[k - 1] = W2(RAD, k) * P.inv_h[1] * P.inv_h[2] / (4.0 * DEN2(RAD));
     }
-    hipLaunchKernelGGL((k_rk3_tiled<PREC, RAD>), dim3(plan_blocks(plan)), dim3(NT), lds, st, g,
-                       P, sc, plan, s, (const T*)f_in, (T*)f_out, (T*)w, (T*)comp, dt);
+    if (nbox == 1)
+        hipLaunchKernelGGL((k_rk3_tiled<PREC, RAD, false>), dim3(plan_blocks(plan)), dim3(NT), lds,
+                           st, g, P, sc, plan_map(plan), s, (const T*)f_in, (T*)f_out, (T*)w,
+                           (T*)comp, dt, plan.box[0], TilePlan{});
+    else
+        hipLaunchKernelGGL((k_rk3_tiled<PREC, RAD, true>), dim3(plan_blocks(plan)), dim3(NT), lds,
+                           st, g, P, sc, TileMap{}, s, (const T*)f_in, (T*)f_out, (T*)w, (T*)comp,
+                           dt, Box{}, plan);
     return hipGetLastError();
 }
 

@@ -514,8 +514,13 @@ __global__ __launch_bounds__(WG_THR) void k_wgrad(const uint16_t* __restrict__ x
     // accumulator sets of wave wv (9 waves): CIN 32: the taps with x shift
     // dx = wv/3 - 1 and z offset dz = wv%3 - 1, one set per dy = -1, 0, 1, so
     // the three share each dz fragment; CIN 8: tap group g = wv (g = 3*dxi +
-    // gi, gi selects 4 of the 9 (dz, dy) pairs)
-    constexpr int NSET = CIN == 32 ? 3 : 1;
+    // gi, gi selects 4 of the 9 (dz, dy) pairs).  CIN 32 with 8 output
+    // channels: the 32 rows of the one set are (dx shift, o) pairs, rows
+    // 8 (dx + 1) + o, the last 8 rows zero, for the taps with dz = wv%3 - 1
+    // and dy = wv/3 - 1 (three times fewer products than three sets of 8
+    // channels padded to 32).
+    constexpr bool PACK_DX = CIN == 32 && COUT == 8;
+    constexpr int NSET = CIN == 32 && !PACK_DX ? 3 : 1;
     floatx16 acc[NSET];
 #pragma unroll
     for (int i = 0; i < NSET; ++i) acc[i] = floatx16{};
@@ -536,12 +541,19 @@ __global__ __launch_bounds__(WG_THR) void k_wgrad(const uint16_t* __restrict__ x
         }
         const int sb[3] = {p % 3, (p + 1) % 3, (p + 2) % 3};  // ring slot of plane dz = -1, 0, 1
         const int dxs = wv / 3;  // shift copy s = dx + 1 (both channel counts)
+        // PACK_DX: lane row col = 8 (dx + 1) + o; the rows past the three
+        // shifts read a zero row (o + 8 >= COUT) of the first copy
+        const int arow = PACK_DX ? (col < 24 ? (col >> 3) * 32 + (col & 7) : 8 + (col & 7))
+                                 : dxs * 32 + col;
 #pragma unroll 4
         for (int kc = 0; kc < CONV_CELLS / 16; ++kc) {
             const int cell = kc * 16 + 8 * h;
             const int rr = cell >> logn, xq = cell & (n - 1);
-            const bf16x8 a = frag(ds + (dxs * 32 + col) * DS + rr * n + xq);
-            if constexpr (CIN == 32) {
+            const bf16x8 a = frag(ds + arow * DS + rr * n + xq);
+            if constexpr (PACK_DX) {
+                const uint16_t* xrow = xs + (col * 3 + sb[wv % 3]) * PS + (rr + wv / 3) * n + xq;
+                acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, frag(xrow), acc[0], 0, 0, 0);
+            } else if constexpr (CIN == 32) {
                 const uint16_t* xrow = xs + (col * 3 + sb[wv % 3]) * PS + rr * n + xq;
 #pragma unroll
                 for (int si = 0; si < 3; ++si)  // dy = si - 1
@@ -567,8 +579,13 @@ __global__ __launch_bounds__(WG_THR) void k_wgrad(const uint16_t* __restrict__ x
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int o = 8 * (r >> 2) + 4 * h + (r & 3);
-            int t, c;
-            if constexpr (CIN == 32) {
+            int t, c, oo = o;
+            if constexpr (PACK_DX) {
+                if (o >= 24) continue;
+                oo = o & 7;
+                t = 9 * (wv % 3) + 3 * (wv / 3) + (o >> 3);
+                c = col;
+            } else if constexpr (CIN == 32) {
                 t = 9 * (wv % 3) + 3 * si + wv / 3;  // t = 9 (dz+1) + 3 (dy+1) + (dx+1)
                 c = col;
             } else {
@@ -577,7 +594,7 @@ __global__ __launch_bounds__(WG_THR) void k_wgrad(const uint16_t* __restrict__ x
                 t = 9 * (pr / 3) + 3 * (pr % 3) + wv / 3;
                 c = col & 7;
             }
-            wb[(t * 32 + o) * 32 + c] = acc[si][r];
+            wb[(t * 32 + oo) * 32 + c] = acc[si][r];
         }
     }
 #pragma unroll

@@ -173,9 +173,10 @@ def test_conv_wgrad(nn, cin, cout, n, batch):
     assert ew <= 1e-4 and eb <= 1e-4
 
 
-def test_wgrad_deterministic(nn):
+@pytest.mark.parametrize("cin,cout", [(32, 32), (32, 8)])
+def test_wgrad_deterministic(nn, cin, cout):
     import torch
-    n, batch, cin, cout = 16, 2, 32, 32
+    n, batch = 16, 2
     rng = np.random.default_rng(5)
     cells = batch * n ** 3
     x = torch.from_numpy(rng.standard_normal(cells * cin)).float().cuda().to(torch.bfloat16)

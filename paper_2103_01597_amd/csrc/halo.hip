@@ -28,19 +28,22 @@ struct alignas(sizeof(E) * V) HVec {
     E v[V];
 };
 
+// X: a workgroup covers 32 rows of one interior plane of one field, eight
+// lanes per row (lane c < 2r fills column c of the left halo, c < r, or
+// column c - r of the right halo), so the row and plane come from the
+// launch indices rather than from divisions.
+constexpr int HX_ROWS = 32;
+
 template <typename E>
 __global__ __launch_bounds__(256) void k_halo_x(Grid g, E* __restrict__ fields)
 {
-    const int r = g.r, w = 2 * g.r;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= g.nz * g.ny * w) return;
-    E* f = fields + (int64_t)blockIdx.y * g.fstride;
-    const int cols = w * g.ny;
-    const int zz = t / cols, rem = t - zz * cols;
-    const int yy = rem / w, c = rem - yy * w;
-    const int x = c < r ? c : g.nx + c;
-    const int row = ((r + zz) * g.my + r + yy) * g.mx;
-    f[row + x] = f[row + wrap_index(x, g.nx, r)];
+    const int r = g.r, c = threadIdx.x & 7;
+    const int yy = blockIdx.x * HX_ROWS + (threadIdx.x >> 3);
+    if (c >= 2 * r || yy >= g.ny) return;
+    E* f = fields + (int64_t)blockIdx.z * g.fstride;
+    const int row = ((r + (int)blockIdx.y) * g.my + r + yy) * g.mx;
+    const int dst = c < r ? c : g.nx + c;  // padded halo column
+    f[row + dst] = f[row + wrap_index(dst, g.nx, r)];
 }
 
 template <typename E, int V>
@@ -81,7 +84,8 @@ void launch_halo_typed(const Grid& g, void* fields, hipStream_t st)
 {
     const int w = 2 * g.r;
     auto blocks = [](int n) { return dim3((unsigned)((n + 255) / 256), NQ); };
-    hipLaunchKernelGGL(k_halo_x<E>, blocks(g.nz * g.ny * w), dim3(256), 0, st, g, (E*)fields);
+    hipLaunchKernelGGL(k_halo_x<E>, dim3((unsigned)((g.ny + HX_ROWS - 1) / HX_ROWS), (unsigned)g.nz, NQ),
+                       dim3(256), 0, st, g, (E*)fields);
     hipLaunchKernelGGL((k_halo_y<E, V>), blocks(g.nz * w * (g.mx / V)), dim3(256), 0, st, g,
                        (E*)fields);
     hipLaunchKernelGGL((k_halo_z<E, V>), blocks(w * (g.mxy / V)), dim3(256), 0, st, g,

@@ -44,8 +44,10 @@ namespace {
 
 constexpr int SEG_THREADS = 256;
 
-// Launch geometry: per segment its first workgroup, buffer offset, extents
-// and the interior start of its packed cells and of its halo cells.  The
+// Launch geometry: per segment its first workgroup, buffer offset, extents,
+// the interior start of its packed cells and of its halo cells, and the
+// lanes given to one x-row of the segment (the power of two >= its x length,
+// at most SEG_THREADS; a workgroup covers SEG_THREADS / lanes rows).  The
 // kernel indexes it only with workgroup-uniform values, so it stays in
 // scalar registers.
 struct SegLaunch {
@@ -54,6 +56,7 @@ struct SegLaunch {
     int len[NSEG][3];
     int src[NSEG][3];
     int dst[NSEG][3];
+    int lanes_log2[NSEG];
 };
 
 SegLaunch seg_launch(const Grid& g, const SegTable& t)
@@ -64,8 +67,12 @@ SegLaunch seg_launch(const Grid& g, const SegTable& t)
     for (int k = 0; k < NSEG; ++k) {
         L.blk[k] = blocks;
         L.off[k] = t.off[k];
-        const int64_t per_field = (t.off[k + 1] - t.off[k]) / NQ;
-        blocks += (int)((per_field + SEG_THREADS - 1) / SEG_THREADS);
+        int lg = 0;
+        while ((1 << lg) < t.len[k][0] && (1 << lg) < SEG_THREADS) ++lg;
+        L.lanes_log2[k] = lg;
+        const int64_t rows = (int64_t)t.len[k][1] * t.len[k][2];
+        const int rows_per_block = SEG_THREADS >> lg;
+        blocks += (int)((rows + rows_per_block - 1) / rows_per_block);
         for (int a = 0; a < 3; ++a) {
             const int d = t.dir[k][a];
             L.len[k][a] = t.len[k][a];
@@ -77,9 +84,11 @@ SegLaunch seg_launch(const Grid& g, const SegTable& t)
     return L;
 }
 
-// One thread per packed element of one segment and field (blockIdx.y is the
-// field, so every index within a field fits 32 bits); UNPACK false: boundary
-// layer -> buffer, true: buffer -> halo.
+// A workgroup copies whole x-rows of one segment and field (blockIdx.y is the
+// field, so every index within a field fits 32 bits): each row gets
+// 2^lanes_log2 consecutive lanes, which step through it, so consecutive lanes
+// touch consecutive cells on both sides.  UNPACK false: boundary layer ->
+// buffer, true: buffer -> halo.
 template <typename T, bool UNPACK>
 __global__ __launch_bounds__(SEG_THREADS) void k_segments(Grid g, SegLaunch L,
                                                            T* __restrict__ grid_fields,
@@ -89,22 +98,25 @@ __global__ __launch_bounds__(SEG_THREADS) void k_segments(Grid g, SegLaunch L,
     int k = 0;
 #pragma unroll
     for (int j = 1; j < NSEG; ++j) k += b >= L.blk[j];
-    const unsigned lx = L.len[k][0], ly = L.len[k][1], lz = L.len[k][2];
-    const unsigned e = (unsigned)(b - L.blk[k]) * SEG_THREADS + threadIdx.x;
-    const unsigned per_field = lx * ly * lz;
-    if (e >= per_field) return;
+    const int lx = L.len[k][0], ly = L.len[k][1], lz = L.len[k][2];
+    const int lg = L.lanes_log2[k];
+    const int lanes = 1 << lg;
+    const int row = (b - L.blk[k]) * (SEG_THREADS >> lg) + (threadIdx.x >> lg);
+    if (row >= ly * lz) return;
+    const int z = row / ly, y = row - z * ly;
     const int q = blockIdx.y;
-    const unsigned z = e / (lx * ly), r2 = e - z * (lx * ly);
-    const unsigned y = r2 / lx, x = r2 - y * lx;
-    const int cx = (UNPACK ? L.dst[k][0] : L.src[k][0]) + (int)x;
-    const int cy = (UNPACK ? L.dst[k][1] : L.src[k][1]) + (int)y;
-    const int cz = (UNPACK ? L.dst[k][2] : L.src[k][2]) + (int)z;
-    const int64_t c = (int64_t)q * g.fstride + g.interior + (int64_t)cz * g.mxy + (int64_t)cy * g.mx + cx;
-    const int64_t i = L.off[k] + (int64_t)q * per_field + e;
-    if (UNPACK)
-        grid_fields[c] = buf[i];
-    else
-        buf[i] = grid_fields[c];
+    const int cy = (UNPACK ? L.dst[k][1] : L.src[k][1]) + y;
+    const int cz = (UNPACK ? L.dst[k][2] : L.src[k][2]) + z;
+    const int cx0 = UNPACK ? L.dst[k][0] : L.src[k][0];
+    T* gp = grid_fields + (int64_t)q * g.fstride + g.interior + (int64_t)cz * g.mxy +
+            (int64_t)cy * g.mx + cx0;
+    T* bp = buf + L.off[k] + (int64_t)q * lx * ly * lz + (int64_t)row * lx;
+    for (int x = threadIdx.x & (lanes - 1); x < lx; x += lanes) {
+        if (UNPACK)
+            gp[x] = bp[x];
+        else
+            bp[x] = gp[x];
+    }
 }
 
 template <typename T>

@@ -307,6 +307,19 @@ __device__ __forceinline__ int tile_of_block(int b, int tiles, int round)
     return t < r * round + rem ? t : NO_TILE;
 }
 
+// Whether the LDS kernels may fetch their halo'd planes as aligned pairs of
+// x-neighbours: the padded row length is even (so are a plane and a field),
+// every box starts at an even x, and f_in is aligned to two elements, so
+// every pair the tiles fetch starts on a two-element boundary.
+inline bool pairs_aligned(const Grid& g, const Box* bx, int nbox, const void* f_in, size_t elem)
+{
+    if (g.mx % 2 != 0 || g.fstride % 2 != 0) return false;
+    if (reinterpret_cast<uintptr_t>(f_in) % (2 * elem) != 0) return false;
+    for (int k = 0; k < nbox; ++k)
+        if (bx[k].x0 % 2 != 0) return false;
+    return true;
+}
+
 // One box's tile grid, as a single-box launch passes it.
 struct TileMap {
     int ntx, nty;  // tiles per axis

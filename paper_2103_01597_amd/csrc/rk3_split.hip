@@ -64,8 +64,6 @@ struct SRing {
     static constexpr int HX = TX + 2 * RAD, HY = TY + 2 * RAD, PLANE = HX * HY;
     static constexpr int SLOT = NQ * PLANE;
     static constexpr int NSLOT = RAD + 1;
-    static constexpr int FULL = PLANE / NC;   // plane elements per field every thread of a group loads
-    static constexpr int EXTRA = PLANE % NC;  // threads that load one more
 };
 
 template <int PREC, int RAD>
@@ -109,8 +107,11 @@ struct Scales {
 // MULTI: the launch covers the several boxes of `plan` and each workgroup
 // takes its box and tile grid from there; otherwise one box, `box` and `map`
 // (a separate instantiation, so that the single-box march is compiled as if
-// the plan did not exist).
-template <int PREC, int RAD, bool MULTI>
+// the plan did not exist).  PAIRS: the halo'd planes are fetched and stored
+// into the ring as pairs of x-neighbours (one 16-byte load and LDS store per
+// pair in FP64, half the load instructions); the launch guarantees that every
+// pair is aligned (even padded row length, even box x0, aligned f_in).
+template <int PREC, int RAD, bool MULTI, bool PAIRS>
 __global__ __launch_bounds__((SRing<PREC, RAD>::NTH), blocks_per_cu<PREC>()) void k_rk3_split(Grid g, const Phys* P_dev, Scales<RAD> sc, TileMap map, int s,
                                                      const typename Prec<PREC>::T* __restrict__ fin,
                                                      typename Prec<PREC>::T* __restrict__ fout,
@@ -143,7 +144,7 @@ __global__ __launch_bounds__((SRing<PREC, RAD>::NTH), blocks_per_cu<PREC>()) voi
     using RG = SRing<PREC, RAD>;
     constexpr int TY = RG::TY, NC = RG::NC;
     constexpr int HX = RG::HX, PLANE = RG::PLANE, SLOT = RG::SLOT;
-    constexpr int NSLOT = RG::NSLOT, FULL = RG::FULL, EXTRA = RG::EXTRA;
+    constexpr int NSLOT = RG::NSLOT;
 
     const int tile = MULTI ? multi_tile : tile_of_block(blockIdx.x, map);
     if (tile == NO_TILE) return;  // the whole workgroup exits together
@@ -159,7 +160,6 @@ __global__ __launch_bounds__((SRing<PREC, RAD>::NTH), blocks_per_cu<PREC>()) voi
     const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x / NC);
     const int tid = threadIdx.x - grp * NC, lx = tid % TX, ly = tid / TX;
     const bool active = (x0 + lx < bx1) && (y0 + ly < by1);
-    const bool extra = tid < EXTRA;
 
     auto field_ptr = [&](auto* base, int q) { return base + q * g.fstride; };
     auto at = [](auto* p, unsigned idx) {
@@ -177,42 +177,51 @@ __global__ __launch_bounds__((SRing<PREC, RAD>::NTH), blocks_per_cu<PREC>()) voi
         // ---- per-thread load slots of the halo'd tile plane (clamped into the
         // padded grid for ragged tiles); each group loads its own four fields
         constexpr int q0 = 4 * G;  // first of the group's fields
-        constexpr int NLOAD = FULL + (EXTRA > 0 ? 1 : 0);
+        // a load unit is one cell, or with PAIRS two x-neighbours (rows of HX
+        // cells are HX / 2 pairs)
+        typedef T Pair __attribute__((ext_vector_type(2)));
+        using LT = typename std::conditional<PAIRS, Pair, T>::type;
+        constexpr int W = PAIRS ? 2 : 1;
+        constexpr int HXU = HX / W, UNITS = PLANE / W;
+        constexpr int NF = UNITS / NC, NE = UNITS % NC;
+        constexpr int NLOAD = NF + (NE > 0 ? 1 : 0);
+        const bool extra_u = tid < NE;
         unsigned goff[NLOAD];
 #pragma unroll
         for (int k = 0; k < NLOAD; ++k) {
-            const int e = min(tid + k * NC, PLANE - 1);
-            const int r = e / HX, c = e - r * HX;
-            const int px = min(x0 + c, g.mx - 1), py = min(y0 + r, g.my - 1);
+            const int e = min(tid + k * NC, UNITS - 1);
+            const int r = e / HXU, c = W * (e - r * HXU);
+            const int px = min(x0 + c, g.mx - W), py = min(y0 + r, g.my - 1);
             goff[k] = (unsigned)(py * g.mx + px);
         }
 
-        T pre[4][NLOAD];
+        LT pre[4][NLOAD];
         auto load_plane = [&](int t) {
             const unsigned zo = (unsigned)((t + RAD) * g.mxy);
 #pragma unroll
             for (int k4 = 0; k4 < 4; ++k4) {
                 const T* f = field_ptr(fin, q0 + k4);
 #pragma unroll
-                for (int k = 0; k < FULL; ++k) pre[k4][k] = *at(f, goff[k] + zo);
+                for (int k = 0; k < NF; ++k) pre[k4][k] = *reinterpret_cast<const LT*>(at(f, goff[k] + zo));
             }
-            if constexpr (EXTRA > 0) {
-                if (extra) {
+            if constexpr (NE > 0) {
+                if (extra_u) {
 #pragma unroll
-                    for (int k4 = 0; k4 < 4; ++k4) pre[k4][FULL] = *at(field_ptr(fin, q0 + k4), goff[FULL] + zo);
+                    for (int k4 = 0; k4 < 4; ++k4)
+                        pre[k4][NF] = *reinterpret_cast<const LT*>(at(field_ptr(fin, q0 + k4), goff[NF] + zo));
                 }
             }
         };
         auto store_plane = [&](int slot) {
-            T* base = lds + slot * SLOT + q0 * PLANE + tid;
+            LT* base = reinterpret_cast<LT*>(lds + slot * SLOT + q0 * PLANE) + tid;
 #pragma unroll
             for (int k4 = 0; k4 < 4; ++k4)
 #pragma unroll
-                for (int k = 0; k < FULL; ++k) base[k4 * PLANE + k * NC] = pre[k4][k];
-            if constexpr (EXTRA > 0) {
-                if (extra) {
+                for (int k = 0; k < NF; ++k) base[k4 * UNITS + k * NC] = pre[k4][k];
+            if constexpr (NE > 0) {
+                if (extra_u) {
 #pragma unroll
-                    for (int k4 = 0; k4 < 4; ++k4) base[k4 * PLANE + FULL * NC] = pre[k4][FULL];
+                    for (int k4 = 0; k4 < 4; ++k4) base[k4 * UNITS + NF * NC] = pre[k4][NF];
                 }
             }
         };
@@ -555,15 +564,18 @@ hipError_t launch_one(const Grid& g, const Phys& P, const Phys* P_dev, const Box
     static int round = -1;  // resident workgroups per round on this device
     constexpr size_t lds = lds_bytes<PREC, RAD>();
     if (round < 0) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_rk3_split<PREC, RAD, false>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_rk3_split<PREC, RAD, true>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        const void* kernels[4] = {(const void*)k_rk3_split<PREC, RAD, false, false>,
+                                  (const void*)k_rk3_split<PREC, RAD, false, true>,
+                                  (const void*)k_rk3_split<PREC, RAD, true, false>,
+                                  (const void*)k_rk3_split<PREC, RAD, true, true>};
+        hipError_t e = hipSuccess;
+        for (int k = 0; k < 4 && e == hipSuccess; ++k)
+            e = hipFuncSetAttribute(kernels[k], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds);
         if (e != hipSuccess) return e;
         int per_cu = 0, dev = 0, cus = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rk3_split<PREC, RAD, false>,
-                                                         SRing<PREC, RAD>::NTH, lds);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, k_rk3_split<PREC, RAD, false, false>, SRing<PREC, RAD>::NTH, lds);
         if (e != hipSuccess) return e;
         e = hipGetDevice(&dev);
         if (e != hipSuccess) return e;
@@ -584,14 +596,19 @@ hipError_t launch_one(const Grid& g, const Phys& P, const Phys* P_dev, const Box
         sc.wyz[k - 1] = W2(RAD, k) * P.inv_h[1] * P.inv_h[2] / (4.0 * DEN2(RAD));
     }
     const dim3 grid(plan_blocks(plan)), block(SRing<PREC, RAD>::NTH);
-    if (nbox == 1)
-        hipLaunchKernelGGL((k_rk3_split<PREC, RAD, false>), grid, block, lds, st, g, P_dev, sc,
-                           plan_map(plan), s, (const T*)f_in, (T*)f_out, (T*)w, (T*)comp, dt,
-                           plan.box[0], TilePlan{});
+    const bool pairs = pairs_aligned(g, bx, nbox, f_in, sizeof(T));
+#define MHD_SPLIT_LAUNCH(MULTI, PAIRS, MAP, BOX, PLAN)                                          \
+    hipLaunchKernelGGL((k_rk3_split<PREC, RAD, MULTI, PAIRS>), grid, block, lds, st, g, P_dev, sc, \
+                       MAP, s, (const T*)f_in, (T*)f_out, (T*)w, (T*)comp, dt, BOX, PLAN)
+    if (nbox == 1 && pairs)
+        MHD_SPLIT_LAUNCH(false, true, plan_map(plan), plan.box[0], TilePlan{});
+    else if (nbox == 1)
+        MHD_SPLIT_LAUNCH(false, false, plan_map(plan), plan.box[0], TilePlan{});
+    else if (pairs)
+        MHD_SPLIT_LAUNCH(true, true, TileMap{}, Box{}, plan);
     else
-        hipLaunchKernelGGL((k_rk3_split<PREC, RAD, true>), grid, block, lds, st, g, P_dev, sc,
-                           TileMap{}, s, (const T*)f_in, (T*)f_out, (T*)w, (T*)comp, dt, Box{},
-                           plan);
+        MHD_SPLIT_LAUNCH(true, false, TileMap{}, Box{}, plan);
+#undef MHD_SPLIT_LAUNCH
     return hipGetLastError();
 }
 

@@ -194,3 +194,52 @@ def test_segmented_full_size_equals_step(mhd):
         del f, w
     assert torch.equal(outs[0], outs[1])
     S.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32c"])
+@pytest.mark.parametrize("order", [6, 8])
+def test_pair_and_cell_fetch_paths_agree(mhd, prec, order):
+    """The split kernel fetches its halo'd planes as aligned pairs of
+    x-neighbours when the launch allows it (even padded row, even box x0,
+    input aligned to two elements) and cell by cell otherwise; both paths
+    must give the same bits.  Whole grid (pairs) against the same substep
+    as a box with odd x0 plus the one column before it, and against a copy
+    of the input shifted by one element in memory (both cell by cell)."""
+    import torch
+    n = (64, 40, 24)
+    say(f"pair/cell fetch {prec} order {order} {n}")
+    S = mhd.Solver(*n, prec, "split", order=order)
+    assert S.layout.mx % 2 == 0
+    f0 = inputs.fourier_modes(n, 3, 1e-2, seed=31)
+    f0[1:4] += 0.05 * inputs.fourier_modes(n, 3, 1.0, seed=32)[1:4]
+    fin = S.upload(f0)
+    for s in (0, 1):
+        w_ref = S.zeros()
+        w_ref.copy_(S.upload(0.3 * f0))
+        outs = []
+        # (a) whole grid: pairs
+        out, w = S.empty(), w_ref.clone()
+        comp = S.zeros() if prec == "f32c" else None
+        S.rk3_substep(s, fin, out, w, comp, 1e-3)
+        outs.append((out, w, comp))
+        # (b) x in [1, nx) (odd x0: cell by cell) and x in [0, 1) (pairs)
+        out, w = S.empty(), w_ref.clone()
+        comp = S.zeros() if prec == "f32c" else None
+        S.rk3_substep_box(s, (1, n[0], 0, n[1], 0, n[2]), fin, out, w, comp, 1e-3)
+        S.rk3_substep_box(s, (0, 1, 0, n[1], 0, n[2]), fin, out, w, comp, 1e-3)
+        outs.append((out, w, comp))
+        # (c) the input one element further on in memory: cell by cell
+        big = torch.empty(S.layout.total_elems + 1, dtype=S.torch_dtype, device="cuda")
+        shifted = big[1:]
+        shifted.copy_(fin)
+        out, w = S.empty(), w_ref.clone()
+        comp = S.zeros() if prec == "f32c" else None
+        S.rk3_substep(s, shifted, out, w, comp, 1e-3)
+        outs.append((out, w, comp))
+        torch.cuda.synchronize()
+        ref = [S.interior_view(t).cpu() for t in outs[0] if t is not None]
+        for k in (1, 2):
+            got = [S.interior_view(t).cpu() for t in outs[k] if t is not None]
+            for a, b in zip(ref, got):
+                assert torch.equal(a, b), (s, k)
+    S.close()

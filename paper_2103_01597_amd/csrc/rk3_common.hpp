@@ -307,7 +307,7 @@ __device__ __forceinline__ int tile_of_block(int b, int tiles, int round)
     return t < r * round + rem ? t : NO_TILE;
 }
 
-// Whether the LDS kernels may fetch their halo'd planes as aligned pairs of
+// Whether the split kernel may fetch its halo'd planes as aligned pairs of
 // x-neighbours: the padded row length is even (so are a plane and a field),
 // every box starts at an even x, and f_in is aligned to two elements, so
 // every pair the tiles fetch starts on a two-element boundary.

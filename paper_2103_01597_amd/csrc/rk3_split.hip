@@ -107,10 +107,11 @@ struct Scales {
 // MULTI: the launch covers the several boxes of `plan` and each workgroup
 // takes its box and tile grid from there; otherwise one box, `box` and `map`
 // (a separate instantiation, so that the single-box march is compiled as if
-// the plan did not exist).  PAIRS: the halo'd planes are fetched and stored
-// into the ring as pairs of x-neighbours (one 16-byte load and LDS store per
-// pair in FP64, half the load instructions); the launch guarantees that every
-// pair is aligned (even padded row length, even box x0, aligned f_in).
+// the plan did not exist).  PAIRS: most of each halo'd plane is fetched and
+// stored into the ring as pairs of x-neighbours (one 16-byte load and LDS
+// store per pair in FP64, about half the load instructions); the launch
+// guarantees that every pair is aligned (even padded row length, even box x0,
+// aligned f_in).
 template <int PREC, int RAD, bool MULTI, bool PAIRS>
 __global__ __launch_bounds__((SRing<PREC, RAD>::NTH), blocks_per_cu<PREC>()) void k_rk3_split(Grid g, const Phys* P_dev, Scales<RAD> sc, TileMap map, int s,
                                                      const typename Prec<PREC>::T* __restrict__ fin,
@@ -177,51 +178,65 @@ __global__ __launch_bounds__((SRing<PREC, RAD>::NTH), blocks_per_cu<PREC>()) voi
         // ---- per-thread load slots of the halo'd tile plane (clamped into the
         // padded grid for ragged tiles); each group loads its own four fields
         constexpr int q0 = 4 * G;  // first of the group's fields
-        // a load unit is one cell, or with PAIRS two x-neighbours (rows of HX
-        // cells are HX / 2 pairs)
+        // Load units of the halo'd tile plane: with PAIRS, the first NFP * NC
+        // pairs of x-neighbours (rows of HX cells are HX / 2 pairs; one 2-element
+        // load and LDS store each), then the remaining cells one by one; without,
+        // every cell one by one.  Offsets are clamped into the padded grid for
+        // ragged tiles.
         typedef T Pair __attribute__((ext_vector_type(2)));
-        using LT = typename std::conditional<PAIRS, Pair, T>::type;
-        constexpr int W = PAIRS ? 2 : 1;
-        constexpr int HXU = HX / W, UNITS = PLANE / W;
-        constexpr int NF = UNITS / NC, NE = UNITS % NC;
-        constexpr int NLOAD = NF + (NE > 0 ? 1 : 0);
-        const bool extra_u = tid < NE;
-        unsigned goff[NLOAD];
+        constexpr int HP = HX / 2;
+        constexpr int NFP = PAIRS ? (PLANE / 2) / NC : 0;   // pair slots per thread
+        constexpr int CELLS0 = 2 * NFP * NC;                 // cells the pair slots cover
+        constexpr int NFE = (PLANE - CELLS0) / NC, NEE = (PLANE - CELLS0) % NC;
+        constexpr int NCELL = NFE + (NEE > 0 ? 1 : 0);          // cell slots per thread
+        const bool extra_u = tid < NEE;
+        unsigned poff[NFP > 0 ? NFP : 1], coff[NCELL > 0 ? NCELL : 1];
 #pragma unroll
-        for (int k = 0; k < NLOAD; ++k) {
-            const int e = min(tid + k * NC, UNITS - 1);
-            const int r = e / HXU, c = W * (e - r * HXU);
-            const int px = min(x0 + c, g.mx - W), py = min(y0 + r, g.my - 1);
-            goff[k] = (unsigned)(py * g.mx + px);
+        for (int k = 0; k < NFP; ++k) {
+            const int p = tid + k * NC, r = p / HP, c = 2 * (p - r * HP);
+            const int px = min(x0 + c, g.mx - 2), py = min(y0 + r, g.my - 1);
+            poff[k] = (unsigned)(py * g.mx + px);
+        }
+#pragma unroll
+        for (int k = 0; k < NCELL; ++k) {
+            const int e = min(CELLS0 + tid + k * NC, PLANE - 1);
+            const int r = e / HX, c = e - r * HX;
+            const int px = min(x0 + c, g.mx - 1), py = min(y0 + r, g.my - 1);
+            coff[k] = (unsigned)(py * g.mx + px);
         }
 
-        LT pre[4][NLOAD];
+        Pair prep[4][NFP > 0 ? NFP : 1];
+        T prec_[4][NCELL > 0 ? NCELL : 1];
         auto load_plane = [&](int t) {
             const unsigned zo = (unsigned)((t + RAD) * g.mxy);
 #pragma unroll
             for (int k4 = 0; k4 < 4; ++k4) {
                 const T* f = field_ptr(fin, q0 + k4);
 #pragma unroll
-                for (int k = 0; k < NF; ++k) pre[k4][k] = *reinterpret_cast<const LT*>(at(f, goff[k] + zo));
+                for (int k = 0; k < NFP; ++k) prep[k4][k] = *reinterpret_cast<const Pair*>(at(f, poff[k] + zo));
+#pragma unroll
+                for (int k = 0; k < NFE; ++k) prec_[k4][k] = *at(f, coff[k] + zo);
             }
-            if constexpr (NE > 0) {
+            if constexpr (NEE > 0) {
                 if (extra_u) {
 #pragma unroll
-                    for (int k4 = 0; k4 < 4; ++k4)
-                        pre[k4][NF] = *reinterpret_cast<const LT*>(at(field_ptr(fin, q0 + k4), goff[NF] + zo));
+                    for (int k4 = 0; k4 < 4; ++k4) prec_[k4][NFE] = *at(field_ptr(fin, q0 + k4), coff[NFE] + zo);
                 }
             }
         };
         auto store_plane = [&](int slot) {
-            LT* base = reinterpret_cast<LT*>(lds + slot * SLOT + q0 * PLANE) + tid;
+            T* base = lds + slot * SLOT + q0 * PLANE;
 #pragma unroll
-            for (int k4 = 0; k4 < 4; ++k4)
+            for (int k4 = 0; k4 < 4; ++k4) {
 #pragma unroll
-                for (int k = 0; k < NF; ++k) base[k4 * UNITS + k * NC] = pre[k4][k];
-            if constexpr (NE > 0) {
+                for (int k = 0; k < NFP; ++k) reinterpret_cast<Pair*>(base + k4 * PLANE)[tid + k * NC] = prep[k4][k];
+#pragma unroll
+                for (int k = 0; k < NFE; ++k) base[k4 * PLANE + CELLS0 + tid + k * NC] = prec_[k4][k];
+            }
+            if constexpr (NEE > 0) {
                 if (extra_u) {
 #pragma unroll
-                    for (int k4 = 0; k4 < 4; ++k4) base[k4 * UNITS + NF * NC] = pre[k4][NF];
+                    for (int k4 = 0; k4 < 4; ++k4) base[k4 * PLANE + CELLS0 + tid + NFE * NC] = prec_[k4][NFE];
                 }
             }
         };

@@ -196,10 +196,11 @@ def test_segmented_full_size_equals_step(mhd):
     S.close()
 
 
+@pytest.mark.parametrize("kernel", ["split"])
 @pytest.mark.parametrize("prec", ["f64", "f32c"])
 @pytest.mark.parametrize("order", [6, 8])
-def test_pair_and_cell_fetch_paths_agree(mhd, prec, order):
-    """The split kernel fetches its halo'd planes as aligned pairs of
+def test_pair_and_cell_fetch_paths_agree(mhd, kernel, prec, order):
+    """The split kernel fetches most of its halo'd planes as aligned pairs of
     x-neighbours when the launch allows it (even padded row, even box x0,
     input aligned to two elements) and cell by cell otherwise; both paths
     must give the same bits.  Whole grid (pairs) against the same substep
@@ -207,8 +208,8 @@ def test_pair_and_cell_fetch_paths_agree(mhd, prec, order):
     of the input shifted by one element in memory (both cell by cell)."""
     import torch
     n = (64, 40, 24)
-    say(f"pair/cell fetch {prec} order {order} {n}")
-    S = mhd.Solver(*n, prec, "split", order=order)
+    say(f"pair/cell fetch {kernel} {prec} order {order} {n}")
+    S = mhd.Solver(*n, prec, kernel, order=order)
     assert S.layout.mx % 2 == 0
     f0 = inputs.fourier_modes(n, 3, 1e-2, seed=31)
     f0[1:4] += 0.05 * inputs.fourier_modes(n, 3, 1.0, seed=32)[1:4]

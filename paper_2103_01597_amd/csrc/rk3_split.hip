@@ -578,15 +578,22 @@ hipError_t launch_one(const Grid& g, const Phys& P, const Phys* P_dev, const Box
     using T = typename Prec<PREC>::T;
     static int round = -1;  // resident workgroups per round on this device
     constexpr size_t lds = lds_bytes<PREC, RAD>();
+    // pair fetches measured faster for FP64 only (the FP32 variants' 8-byte
+    // pairs were no faster at order 6 and 9% slower at order 8)
+    constexpr bool PAIRS_OK = PREC == MHD_F64;
     if (round < 0) {
         const void* kernels[4] = {(const void*)k_rk3_split<PREC, RAD, false, false>,
-                                  (const void*)k_rk3_split<PREC, RAD, false, true>,
-                                  (const void*)k_rk3_split<PREC, RAD, true, false>,
-                                  (const void*)k_rk3_split<PREC, RAD, true, true>};
+                                  (const void*)k_rk3_split<PREC, RAD, true, false>, nullptr,
+                                  nullptr};
+        if constexpr (PAIRS_OK) {
+            kernels[2] = (const void*)k_rk3_split<PREC, RAD, false, PAIRS_OK>;
+            kernels[3] = (const void*)k_rk3_split<PREC, RAD, true, PAIRS_OK>;
+        }
         hipError_t e = hipSuccess;
         for (int k = 0; k < 4 && e == hipSuccess; ++k)
-            e = hipFuncSetAttribute(kernels[k], hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)lds);
+            if (kernels[k])
+                e = hipFuncSetAttribute(kernels[k], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)lds);
         if (e != hipSuccess) return e;
         int per_cu = 0, dev = 0, cus = 0;
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
@@ -611,18 +618,22 @@ hipError_t launch_one(const Grid& g, const Phys& P, const Phys* P_dev, const Box
         sc.wyz[k - 1] = W2(RAD, k) * P.inv_h[1] * P.inv_h[2] / (4.0 * DEN2(RAD));
     }
     const dim3 grid(plan_blocks(plan)), block(SRing<PREC, RAD>::NTH);
-    const bool pairs = pairs_aligned(g, bx, nbox, f_in, sizeof(T));
+    const bool pairs = PAIRS_OK && pairs_aligned(g, bx, nbox, f_in, sizeof(T));
 #define MHD_SPLIT_LAUNCH(MULTI, PAIRS, MAP, BOX, PLAN)                                          \
     hipLaunchKernelGGL((k_rk3_split<PREC, RAD, MULTI, PAIRS>), grid, block, lds, st, g, P_dev, sc, \
                        MAP, s, (const T*)f_in, (T*)f_out, (T*)w, (T*)comp, dt, BOX, PLAN)
-    if (nbox == 1 && pairs)
-        MHD_SPLIT_LAUNCH(false, true, plan_map(plan), plan.box[0], TilePlan{});
-    else if (nbox == 1)
+    if (pairs) {
+        if constexpr (PAIRS_OK) {
+            if (nbox == 1)
+                MHD_SPLIT_LAUNCH(false, PAIRS_OK, plan_map(plan), plan.box[0], TilePlan{});
+            else
+                MHD_SPLIT_LAUNCH(true, PAIRS_OK, TileMap{}, Box{}, plan);
+        }
+    } else if (nbox == 1) {
         MHD_SPLIT_LAUNCH(false, false, plan_map(plan), plan.box[0], TilePlan{});
-    else if (pairs)
-        MHD_SPLIT_LAUNCH(true, true, TileMap{}, Box{}, plan);
-    else
+    } else {
         MHD_SPLIT_LAUNCH(true, false, TileMap{}, Box{}, plan);
+    }
 #undef MHD_SPLIT_LAUNCH
     return hipGetLastError();
 }

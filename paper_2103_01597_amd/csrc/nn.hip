@@ -921,15 +921,11 @@ hipError_t launch_conv(const uint16_t* x, const uint16_t* w, const float* bias, 
                        int n, int batch, int cout, uint16_t* o0, uint16_t* o1, float* of,
                        hipStream_t st)
 {
-    static bool attr = false;
-    if (!attr) {
-        const int most = (int)(conv_lds(CIN, 16) > conv_lds(CIN, 64) ? conv_lds(CIN, 16)
-                                                                      : conv_lds(CIN, 64));
-        hipError_t e = hipFuncSetAttribute((const void*)k_conv<CIN, MODE>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, most);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
+    // once per instantiation (thread-safe static initialisation)
+    static const hipError_t attr = hipFuncSetAttribute(
+        (const void*)k_conv<CIN, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (int)(conv_lds(CIN, 16) > conv_lds(CIN, 64) ? conv_lds(CIN, 16) : conv_lds(CIN, 64)));
+    if (attr != hipSuccess) return attr;
     int columns, nch, zc;
     conv_chunks(n, batch, columns, nch, zc);
     hipLaunchKernelGGL((k_conv<CIN, MODE>), dim3(columns * nch), dim3(CONV_THR),
@@ -941,15 +937,10 @@ hipError_t launch_conv(const uint16_t* x, const uint16_t* w, const float* bias, 
 hipError_t launch_conv_out8(const uint16_t* x, const uint16_t* w, const float* bias, int n,
                             int batch, float* of, hipStream_t st)
 {
-    static bool attr = false;
-    if (!attr) {
-        const int most = (int)(conv_lds(32, 16) > conv_lds(32, 64) ? conv_lds(32, 16)
-                                                                   : conv_lds(32, 64));
-        hipError_t e = hipFuncSetAttribute((const void*)k_conv_out8,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, most);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
+    static const hipError_t attr = hipFuncSetAttribute(
+        (const void*)k_conv_out8, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (int)(conv_lds(32, 16) > conv_lds(32, 64) ? conv_lds(32, 16) : conv_lds(32, 64)));
+    if (attr != hipSuccess) return attr;
     int columns, nch, zc;
     conv_chunks(n, batch, columns, nch, zc);
     hipLaunchKernelGGL(k_conv_out8, dim3(columns * nch), dim3(CONV_THR), conv_lds(32, n), st, x,
@@ -961,15 +952,10 @@ template <int CIN, int COUT>
 hipError_t launch_wgrad(const uint16_t* x, const uint16_t* dz, int n, int batch, float* ws,
                         float* dw, float* db, hipStream_t st)
 {
-    static bool attr = false;
-    if (!attr) {
-        const int m = (int)(wgrad_lds(CIN, 16) > wgrad_lds(CIN, 64) ? wgrad_lds(CIN, 16)
-                                                                     : wgrad_lds(CIN, 64));
-        hipError_t e = hipFuncSetAttribute((const void*)k_wgrad<CIN, COUT>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, m);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
+    static const hipError_t attr = hipFuncSetAttribute(
+        (const void*)k_wgrad<CIN, COUT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (int)(wgrad_lds(CIN, 16) > wgrad_lds(CIN, 64) ? wgrad_lds(CIN, 16) : wgrad_lds(CIN, 64)));
+    if (attr != hipSuccess) return attr;
     int columns, nch, zc;
     conv_chunks(n, batch, columns, nch, zc);
     const int blocks = columns * nch;

@@ -576,12 +576,17 @@ hipError_t launch_one(const Grid& g, const Phys& P, const Phys* P_dev, const Box
                       hipStream_t st)
 {
     using T = typename Prec<PREC>::T;
-    static int round = -1;  // resident workgroups per round on this device
     constexpr size_t lds = lds_bytes<PREC, RAD>();
     // pair fetches measured faster for FP64 only (the FP32 variants' 8-byte
     // pairs were no faster at order 6 and 9% slower at order 8)
     constexpr bool PAIRS_OK = PREC == MHD_F64;
-    if (round < 0) {
+    // once per instantiation (thread-safe static initialisation): the LDS
+    // limit of every variant, and the workgroups resident at once (a round)
+    struct Setup {
+        hipError_t err;
+        int round;
+    };
+    static const Setup setup = []() -> Setup {
         const void* kernels[4] = {(const void*)k_rk3_split<PREC, RAD, false, false>,
                                   (const void*)k_rk3_split<PREC, RAD, true, false>, nullptr,
                                   nullptr};
@@ -594,17 +599,16 @@ hipError_t launch_one(const Grid& g, const Phys& P, const Phys* P_dev, const Box
             if (kernels[k])
                 e = hipFuncSetAttribute(kernels[k], hipFuncAttributeMaxDynamicSharedMemorySize,
                                         (int)lds);
-        if (e != hipSuccess) return e;
         int per_cu = 0, dev = 0, cus = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, k_rk3_split<PREC, RAD, false, false>, SRing<PREC, RAD>::NTH, lds);
-        if (e != hipSuccess) return e;
-        e = hipGetDevice(&dev);
-        if (e != hipSuccess) return e;
-        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (e != hipSuccess) return e;
-        round = per_cu * cus;
-    }
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, k_rk3_split<PREC, RAD, false, false>, SRing<PREC, RAD>::NTH, lds);
+        if (e == hipSuccess) e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        return Setup{e, per_cu * cus};
+    }();
+    if (setup.err != hipSuccess) return setup.err;
+    const int round = setup.round;
     const TilePlan plan =
         plan_tiles(bx, nbox, SRing<PREC, RAD>::TX, SRing<PREC, RAD>::TY, round);
     Scales<RAD> sc{};

@@ -485,26 +485,30 @@ hipError_t launch_one(const Grid& g, const Phys& P, const Box* bx, int nbox, int
                       hipStream_t st)
 {
     using T = typename Prec<PREC>::T;
-    static int round = -1;  // resident workgroups per round on this device
     constexpr size_t lds = lds_bytes<PREC, RAD>();
     constexpr int TY = Ring<PREC, RAD>::TY, NT = Ring<PREC, RAD>::NT;
-    if (round < 0) {
+    // once per instantiation (thread-safe static initialisation): the LDS
+    // limit of both variants, and the workgroups resident at once (a round)
+    struct Setup {
+        hipError_t err;
+        int round;
+    };
+    static const Setup setup = []() -> Setup {
         hipError_t e = hipFuncSetAttribute((const void*)k_rk3_tiled<PREC, RAD, false>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e == hipSuccess)
             e = hipFuncSetAttribute((const void*)k_rk3_tiled<PREC, RAD, true>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
         int per_cu = 0, dev = 0, cus = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rk3_tiled<PREC, RAD, false>,
-                                                         NT, lds);
-        if (e != hipSuccess) return e;
-        e = hipGetDevice(&dev);
-        if (e != hipSuccess) return e;
-        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (e != hipSuccess) return e;
-        round = per_cu * cus;
-    }
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rk3_tiled<PREC, RAD, false>,
+                                                             NT, lds);
+        if (e == hipSuccess) e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        return Setup{e, per_cu * cus};
+    }();
+    if (setup.err != hipSuccess) return setup.err;
+    const int round = setup.round;
     const TilePlan plan = plan_tiles(bx, nbox, TX, TY, round);
     Scales<RAD> sc{};
     for (int a = 0; a < 3; ++a) {

@@ -156,6 +156,35 @@ def test_segmented_step_equals_step(mhd, prec, n, same_stream):
     S.close()
 
 
+@pytest.mark.parametrize("order", [2, 4, 8])
+@pytest.mark.parametrize("prec", ["f64", "f32c"])
+@pytest.mark.parametrize("n", [(48, 40, 24), (19, 6, 11), (70, 20, 36), (8, 5, 9)])
+def test_segmented_step_equals_step_other_orders(mhd, order, prec, n):
+    """The segmented step at stencil orders 2, 4 and 8: segments, halo and
+    the z faces of the outer shell are r = order / 2 cells thick (the kernel
+    AUTO picks, and at order 8 its 32 x 4 FP64 tile, change with them);
+    bit for bit the monolithic step, over two steps."""
+    import torch
+    say(f"segmented step order {order} {prec} {n}")
+    S = mhd.Solver(*n, prec, order=order)
+    f0 = inputs.fourier_modes(n, 3, 0.05, seed=25)
+    res = []
+    comm = torch.cuda.Stream()
+    for segmented in (False, True):
+        f = [S.upload(f0), S.empty()]
+        w = S.zeros()
+        comp = S.zeros() if prec == "f32c" else None
+        if segmented:
+            cur = S.step_segmented(f, 0, w, comp, 1e-3, 2, comm_stream=comm)
+        else:
+            cur = S.step(f, 0, w, comp, 1e-3, 2)
+        torch.cuda.synchronize()
+        res.append((cur, S.interior_view(f[cur]).cpu().numpy(), S.interior_view(w).cpu().numpy()))
+    assert res[0][0] == res[1][0]
+    assert np.array_equal(res[0][1], res[1][1]) and np.array_equal(res[0][2], res[1][2])
+    S.close()
+
+
 def test_segmented_step_against_oracle(mhd):
     import torch
     n = (32, 32, 32)

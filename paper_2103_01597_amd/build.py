@@ -8,7 +8,9 @@ ILP strategy: they are bound by instruction latency, and it measured up to
 4-7% faster at 512^3 than the default scheduler (the strategy only reorders
 instructions; the results do not change).  The instantiations it slows are
 compiled from rk3_split_dflt.hip and rk3_tiled_dflt.hip, which include the
-kernel files with MHD_DEFAULT_SCHED, with the default scheduler.
+kernel files with MHD_DEFAULT_SCHED, with the default scheduler.  The FP64
+sixth-order split kernel comes from rk3_split_f64r3.hip (the same kernel
+file, its plane step compiled as a lambda; ILP scheduler).
 """
 import glob
 import os
@@ -29,6 +31,7 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
 # extra flags per source file
 PER_FILE = {
     "rk3_split.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
+    "rk3_split_f64r3.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
     "rk3_tiled.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
 }
 

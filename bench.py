@@ -29,7 +29,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-KERNEL_SOURCE = {"split": "rk3_split.hip", "tiled": "rk3_tiled.hip", "direct": "rk3_direct.hip"}
+# translation units each fused kernel is built from (the _dflt and _f64r3
+# units include the kernel file and build some of its instantiations)
+KERNEL_SOURCE = {"split": ("rk3_split.hip", "rk3_split_f64r3.hip", "rk3_split_dflt.hip"),
+                 "tiled": ("rk3_tiled.hip", "rk3_tiled_dflt.hip"), "direct": ("rk3_direct.hip",)}
 KERNEL_SYMBOL = {"split": "k_rk3_split", "tiled": "k_rk3_tiled", "direct": "k_rk3_direct"}
 
 WORKLOAD_TEXT = {
@@ -222,11 +225,12 @@ def kernel_source_hash(kernel):
     from paper_2103_01597_amd import build as hip_build
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2103_01597_amd", "csrc")
-    for name in (KERNEL_SOURCE[kernel], "rk3_common.hpp", "mhd_internal.hpp"):
+    for name in (*KERNEL_SOURCE[kernel], "rk3_common.hpp", "mhd_internal.hpp"):
         with open(os.path.join(csrc, name), "rb") as fh:
             h.update(fh.read())
-    flags = hip_build.FLAGS + hip_build.PER_FILE.get(KERNEL_SOURCE[kernel], [])
-    h.update(" ".join(f for f in flags if not f.startswith("/")).encode())
+    for unit in KERNEL_SOURCE[kernel]:
+        flags = hip_build.FLAGS + hip_build.PER_FILE.get(unit, [])
+        h.update(" ".join(f for f in flags if not f.startswith("/")).encode())
     return h.hexdigest()
 
 

@@ -57,6 +57,23 @@ namespace {
 #ifndef MHD_SPLIT_BODY_LAMBDA
 #define MHD_SPLIT_BODY_LAMBDA 0
 #endif
+// The physics constants are read per plane through P_dev.  Declared
+// __restrict__ (nothing the kernel stores can alias them) the reads become
+// scalar-memory loads, counted apart from the vector-memory loads and
+// stores; through a plain pointer they are vector loads, and the wait for
+// them also waits for the next plane's prefetch issued before them (group
+// M reads the constants in its derivative phase).  Scalar loads measured
+// 1.2% faster for FP64 at order 6 and 1.6% at order 4 (512^3 and 256^3),
+// 1.2% slower for FP64 at order 8, which rk3_split_dflt.hip builds with
+// MHD_SPLIT_PHYS_SMEM 0.
+#ifndef MHD_SPLIT_PHYS_SMEM
+#define MHD_SPLIT_PHYS_SMEM 1
+#endif
+#if MHD_SPLIT_PHYS_SMEM
+#define SPLIT_PHYS_PTR const Phys* __restrict__
+#else
+#define SPLIT_PHYS_PTR const Phys*
+#endif
 #ifndef MHD_SPLIT_TX
 #define MHD_SPLIT_TX 32
 #endif
@@ -125,7 +142,7 @@ struct Scales {
 // guarantees that every pair is aligned (even padded row length, even box x0,
 // aligned f_in).
 template <int PREC, int RAD, bool MULTI, bool PAIRS>
-__global__ __launch_bounds__((SRing<PREC, RAD>::NTH), blocks_per_cu<PREC>()) void k_rk3_split(Grid g, const Phys* P_dev, Scales<RAD> sc, TileMap map, int s,
+__global__ __launch_bounds__((SRing<PREC, RAD>::NTH), blocks_per_cu<PREC>()) void k_rk3_split(Grid g, SPLIT_PHYS_PTR P_dev, Scales<RAD> sc, TileMap map, int s,
                                                      const typename Prec<PREC>::T* __restrict__ fin,
                                                      typename Prec<PREC>::T* __restrict__ fout,
                                                      typename Prec<PREC>::T* __restrict__ w,

@@ -225,6 +225,38 @@ def test_segmented_full_size_equals_step(mhd):
     S.close()
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32c"])
+def test_segmented_benchmark_size_equals_step(mhd, prec):
+    """512^3 with the benchmark's state and kernels (the configuration
+    bench.py times for its segmented figure): one segmented step equals one
+    mhd_step bit for bit, state and register (and, for FP32C, the
+    compensation)."""
+    import torch
+    n = (512, 512, 512)
+    say(f"segmented vs step at 512^3 {prec}")
+    S = mhd.Solver(*n, prec)
+    f0 = inputs.workload_state("prec512")
+    comm = torch.cuda.Stream()
+    outs = []
+    for segmented in (False, True):
+        f = [S.upload(f0), S.empty()]
+        w = S.zeros()
+        comp = S.zeros() if prec == "f32c" else None
+        if segmented:
+            cur = S.step_segmented(f, 0, w, comp, 1e-3, 1, comm_stream=comm)
+        else:
+            cur = S.step(f, 0, w, comp, 1e-3, 1)
+        torch.cuda.synchronize()
+        outs.append((cur, S.interior_view(f[cur]).clone(), S.interior_view(w).clone(),
+                     None if comp is None else S.interior_view(comp).clone()))
+        del f, w, comp
+    assert outs[0][0] == outs[1][0]
+    for k in (1, 2, 3):
+        if outs[0][k] is not None:
+            assert torch.equal(outs[0][k], outs[1][k])
+    S.close()
+
+
 @pytest.mark.parametrize("kernel", ["split"])
 @pytest.mark.parametrize("prec", ["f64", "f32c"])
 @pytest.mark.parametrize("order", [6, 8])

@@ -1,12 +1,12 @@
 """Oracle values at sampled cells of a grid too large for the oracle.
 
 A cell's state after k substeps depends only on the initial state within
-3k cells of it (each substep reads a stencil of radius 3).  So for every
-sampled cell the oracle runs the k substeps on a small periodic block (side
-at least 2*3k + 1, same grid spacing) cut, with periodic wrap, from the
-full initial state around that cell; the value there is then exactly the
-full-grid oracle's (the block's own periodic wrap only corrupts cells
-within 3j of its faces after j substeps).  The input is the seeded initial state; nothing comes
+rk cells of it (each substep reads a stencil of radius r = order / 2, 3 at
+sixth order).  So for every sampled cell the oracle runs the k substeps on
+a small periodic block (side at least 2rk + 1, same grid spacing) cut, with
+periodic wrap, from the full initial state around that cell; the value
+there is then exactly the full-grid oracle's (the block's own periodic wrap
+only corrupts cells within rj of its faces after j substeps).  The input is the seeded initial state; nothing comes
 from the GPU path.
 """
 from __future__ import annotations
@@ -18,8 +18,6 @@ import numpy as np
 
 import oracle
 from paper_2103_01597_amd import inputs
-
-R = 3
 
 
 def _block_side(length, n, r):
@@ -42,7 +40,7 @@ def block_reference(f0, cells, p: "oracle.Params", dt: float, nsub: int):
     RK3 steps (substep index cycling 0, 1, 2)."""
     k, j, i = (np.asarray(a, dtype=np.int64) for a in cells)
     nz, ny, nx = f0.shape[1:]
-    r = R * nsub
+    r = (p.order // 2) * nsub
     (mx, lx), (my, ly), (mz, lz) = (_block_side(p.lx, nx, r), _block_side(p.ly, ny, r),
                                     _block_side(p.lz, nz, r))
     if mx > nx or my > ny or mz > nz:
@@ -81,21 +79,22 @@ def sample_cells(n, ncells, seed):
 _CACHE = {}
 
 
-def workload_reference(wl_name, ncells=400, seed=0, fp32_state=False):
+def workload_reference(wl_name, ncells=400, seed=0, fp32_state=False, order=6):
     """(params, initial state, cells, fs, ws, per-field max |f0|) for one
     RK3 step of a named workload, fs/ws from block_reference.  With
     fp32_state the initial state is first rounded to FP32 (the state an
     FP32-storage run starts from), so that a comparison measures the
-    arithmetic and storage of the run, not the rounding of its input.  The
+    arithmetic and storage of the run, not the rounding of its input; order
+    is the stencil order of the oracle (and of the run compared).  The
     most recent workload is cached (the state of a large one is
     gigabytes)."""
-    key = (wl_name, ncells, seed, fp32_state)
+    key = (wl_name, ncells, seed, fp32_state, order)
     if key not in _CACHE:
         _CACHE.clear()
         wl = inputs.WORKLOADS[wl_name]
         n = wl["shape"]
         lengths = wl.get("lengths", (2 * math.pi,) * 3)
-        p = oracle.Params(*n, lx=lengths[0], ly=lengths[1], lz=lengths[2])
+        p = oracle.Params(*n, lx=lengths[0], ly=lengths[1], lz=lengths[2], order=order)
         f0 = inputs.workload_state(wl_name)
         if fp32_state:
             f0 = f0.astype(np.float32).astype(np.float64)

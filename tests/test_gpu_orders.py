@@ -141,6 +141,35 @@ def test_f32_step_against_oracle(mhd, shape, order, kernel):
     assert max(e) <= TOL_F32
 
 
+@pytest.mark.parametrize("order", [2, 4, 8])
+def test_order_study_size_sampled(mhd, order):
+    """The order study's configuration (256^3, the sub256 state, FP64, the
+    kernel AUTO picks, mhd_step): one RK3 step compared at 100 sampled cells
+    with the oracle at the same order run on dependence blocks of the
+    initial state (radius 3r around each cell after the three substeps)."""
+    import torch
+    from oracle_blocks import workload_reference
+    wl = inputs.WORKLOADS["sub256"]
+    n = wl["shape"]
+    p, f0, cells, fs, ws, scale = workload_reference("sub256", 100, 1, order=order)
+    S = mhd.Solver(*n, "f64", None, order=order, **_phys_kw(p))
+    say(f"sampled 256^3 order {order}: kernel {S.kernel}")
+    bufs = [S.upload(f0), S.empty()]
+    w = S.zeros()
+    cur = S.step(bufs, 0, w, None, wl["dt"], 1)
+    torch.cuda.synchronize()
+    idx = (slice(None),) + tuple(torch.as_tensor(a) for a in cells)
+    gf = S.interior_view(bufs[cur])[idx].cpu().numpy()
+    gw = S.interior_view(w)[idx].cpu().numpy()
+    S.close()
+    ef = [np.max(np.abs(gf[q] - fs[2, q])) / scale[q] for q in range(8)]
+    ew = [np.max(np.abs(gw[q] - ws[2, q])) / max(np.max(np.abs(ws[2, q])), 1e-300)
+          for q in range(8)]
+    say("  f rel err:", ["%.2e" % e for e in ef])
+    say("  w rel err:", ["%.2e" % e for e in ew])
+    assert max(ef) <= TOL_F64 and max(ew) <= TOL_F64
+
+
 def test_orders_differ(mhd):
     """The order really reaches the kernels: at a coarse resolution the
     results of different orders differ far beyond rounding."""
